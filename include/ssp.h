@@ -1,0 +1,186 @@
+/*
+ * ssp.h -- C ABI of libssp, an MI355X (gfx950) library that steps large
+ * ensembles of independent single-chain slip-spring chains (Uneyama,
+ * "Single Chain Slip-Spring Model for Fast Rheology Simulations of Entangled
+ * Polymers on GPU") and reduces their stress into the relaxation modulus G(t)
+ * and per-element viscosity growth.
+ *
+ * Model (units b = kBT = zeta = 1, Sec. 3.1):
+ *   free energy  F = sum_i 3/2 (R_{i+1}-R_i)^2 + sum_j 3/(2 N_s) (R_{S_j}-A_j)^2
+ *                (Sec. 2.1, free-energy equation);
+ *   Langevin     dR_i/dt = -dJ/dR_i + kappa.R_i + xi_i, dA_j/dt = kappa.A_j
+ *                (Sec. 2.2), integrated by the three-substep Euler scheme of
+ *                Sec. 3.1: Euler-Maruyama move, slip-spring hop, then
+ *                construction/destruction at the chain ends with K = C - Z
+ *                attempts (Sec. 3.2);
+ *   stress       sigma = sum_i 3 b_i b_i - N 1 (Sec. 2.1 stress equation),
+ *                virtual stress sigma^v = sum_j (3/N_s) d_j d_j - Z 1 with
+ *                d_j = R_{S_j} - A_j (Appendix B);
+ *   modulus      G(t) = <sigma(t) [sigma(0) + sigma^v(0)]> per chain in kBT
+ *                units (Sec. 2.3, Green-Kubo form of the relaxation modulus).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns 0 on success or a negative SSP_E* code.  No C++
+ *    exception crosses the ABI.  ssp_last_error() gives a message for the
+ *    last failure on a handle (or, with NULL, the last failure of
+ *    ssp_create/ssp_query_sizes on the calling thread).
+ *  - Pointers named *_dev are device pointers on the GPU current at
+ *    ssp_create; *_host are host pointers.  The caller owns every buffer;
+ *    the library never frees caller memory.
+ *  - Work is enqueued on the caller's stream and returns without waiting,
+ *    except where a function says it synchronises.  Stream 0 (the null
+ *    stream) is accepted.
+ *  - A handle is not thread-safe.  Separate handles are independent.
+ *  - Chains are numbered 0..n_chains-1 and grouped by element: the chains of
+ *    element e are [element_offsets[e], element_offsets[e+1]).
+ *  - Bead i (0-based) of chain k and slot j of chain k are entry off_k + i
+ *    (resp. off_k + j) of the canonical state view, off_k = sum_{k'<k} N_k'.
+ *    Slot capacity C = N per chain, one slot per bead (Sec. 3.2).
+ */
+#ifndef SSP_H
+#define SSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSP_OK 0
+#define SSP_EINVAL (-1)      /* invalid argument or configuration */
+#define SSP_ESIZE (-2)       /* buffer too small or size overflow */
+#define SSP_EHIP (-3)        /* a HIP runtime call failed */
+#define SSP_ENONFINITE (-4)  /* a non-finite bead position was produced */
+#define SSP_ESTATE (-5)      /* call made in the wrong order */
+
+#define SSP_FP32 0 /* FP32 dynamics with compensated (hi, lo) position sums; FP64 stress */
+#define SSP_FP64 1 /* FP64 throughout */
+
+#define SSP_MAX_BEADS 128
+
+typedef struct ssp_handle ssp_handle;
+typedef void* ssp_stream; /* a hipStream_t */
+
+typedef struct ssp_config {
+    int64_t n_chains;               /* M >= 1 */
+    int32_t n_elements;             /* E >= 1 */
+    int32_t precision;              /* SSP_FP32 or SSP_FP64 */
+    const int32_t* n_beads_host;    /* [M], 2 <= N_k <= SSP_MAX_BEADS; NULL: all equal to n_beads */
+    int32_t n_beads;                /* N used when n_beads_host is NULL */
+    int32_t sample_every;           /* n_s >= 1: stress sampled after every n_s-th step */
+    const int32_t* element_offsets_host; /* [E+1], 0 = off[0] < ... <= off[E] = M; NULL: equal split */
+    const int64_t* chain_ids_host;  /* [M] global chain ids keying the random streams; NULL: 0..M-1 */
+    double dt;                      /* time step, > 0 (Sec. 3.1) */
+    double n0;                      /* N_0: <Z>_eq = N/N_0, > 0 (Sec. 2.1) */
+    double ns;                      /* N_s: slip-spring strength, > 0 (Sec. 2.1) */
+    double zeta_s;                  /* slip-spring friction, > 0 (Sec. 2.2) */
+    uint64_t seed;                  /* Philox key */
+    int32_t max_steps_per_launch;   /* steps per kernel launch inside ssp_step; 0 = automatic */
+    int32_t corr_levels;            /* multiple-tau levels (0 disables the correlator), <= 16 */
+    int32_t corr_lags;              /* lags per level; must be 16 when the correlator is on */
+    int32_t corr_batches;           /* chain groups for batch-means errors, 1..64 */
+    int64_t series_capacity;        /* samples kept per element (0 disables the element series) */
+    int32_t use_graph;              /* 1: ssp_step replays a captured hipGraph; 0: plain launches */
+    int32_t reserved[7];
+} ssp_config;
+
+/* Fills *cfg with the paper's standard parameters (Sec. 4.1): N_0 = 4,
+ * N_s = 0.5, zeta_s = 0.1, dt = 0.01, plus n_chains = 1, n_elements = 1,
+ * n_beads = 8, precision FP32, sample_every = 1, seed = 1, corr_levels 16,
+ * corr_lags 16, corr_batches 16, series_capacity 0, use_graph 1. */
+int ssp_config_init(ssp_config* cfg);
+
+/* Bytes the caller must allocate on the device for the state and the work
+ * buffer of *cfg.  Both must be 256-byte aligned.  Fails with SSP_EINVAL on
+ * an invalid configuration (message via ssp_last_error(NULL)). */
+int ssp_query_sizes(const ssp_config* cfg, size_t* state_bytes, size_t* work_bytes);
+
+/* Validates *cfg, copies its host tables into work_dev (synchronously, on
+ * the null stream), and returns a handle.  state_dev/work_dev must stay
+ * allocated until ssp_destroy; the handle owns only host-side metadata,
+ * compiled graphs and one internal capture stream.  The step counter starts
+ * at 0. */
+int ssp_create(const ssp_config* cfg, void* state_dev, void* work_dev, ssp_handle** out);
+
+/* Samples the equilibrium initial state of every chain (Sec. 3.1, sampling
+ * procedure): Gaussian bonds of variance 1/3 per component with R_0 = 0,
+ * Z from Poisson(N/N_0) truncated to 0..N, S uniform on the beads, anchors
+ * Gaussian about R_S with variance N_s/3 per component.  Resets the step
+ * counter, the correlator and the element series. */
+int ssp_init_equilibrium(ssp_handle* h, ssp_stream stream);
+
+/* Advances every chain by n_steps >= 0 steps of the three-substep scheme
+ * (Sec. 3.1) under the velocity gradient kappa_dev: [E][9] row-major FP64,
+ * (kappa.R)_a = sum_b kappa[e][3a+b] R_b, constant over the call (a step
+ * strain gamma is ssp_step(h, 1, gamma/dt in xy) followed by kappa = 0).
+ * Stress is sampled after every step whose 1-based count is a multiple of
+ * sample_every; samples feed the correlator and the element series.
+ * Asynchronous.  A non-finite position latches a device flag reported by the
+ * next ssp_read_* call. */
+int ssp_step(ssp_handle* h, int64_t n_steps, const double* kappa_dev, ssp_stream stream);
+
+/* Per-chain stress of the current state, out_dev: [M][12] FP64 = sigma
+ * (xx, yy, zz, xy, yz, zx) then sigma^v in the same order (Sec. 2.1 stress
+ * equation; Appendix B virtual stress).  Synchronises the stream; returns
+ * SSP_ENONFINITE if the non-finite flag is set. */
+int ssp_read_stress(ssp_handle* h, double* out_dev, ssp_stream stream);
+
+/* Canonical FP64 view of the state: R_dev [sum N][3], A_dev [sum N][3]
+ * (hi + lo for the FP32 path), S_dev [sum N] int32 (bead index 0..N-1, or
+ * -1 for an empty slot).  Positions may have been shifted by a common
+ * per-chain vector (re-centring); every physical quantity depends only on
+ * R_i - R_i' and R_{S_j} - A_j, which the shift leaves unchanged.
+ * Synchronises the stream. */
+int ssp_read_state(ssp_handle* h, double* R_dev, double* A_dev, int32_t* S_dev, ssp_stream stream);
+
+/* Overwrites the state from a canonical FP64 view (same layout as
+ * ssp_read_state).  S must be -1 or in 0..N_k-1.  Does not reset counters. */
+int ssp_write_state(ssp_handle* h, const double* R_dev, const double* A_dev, const int32_t* S_dev,
+                    ssp_stream stream);
+
+/* Per element e and sample t (t = 0 is the first sample after the last
+ * ssp_init_equilibrium or ssp_reset_observables), out_dev[e][t][0..5] =
+ * sum over the chains of e of sigma (xx, yy, zz, xy, yz, zx), summed with
+ * Neumaier-compensated FP64.  The viscosity growth of a shear element is
+ * out[e][t][3] / (M_e gamma_dot_e) (Sec. 4.1, viscosity growth).  out_dev
+ * holds [E][series_capacity][6]; *n_samples_host receives the number of
+ * valid samples (<= series_capacity).  Synchronises the stream. */
+int ssp_read_element_series(ssp_handle* h, double* out_dev, int64_t* n_samples_host, ssp_stream stream);
+
+/* Relaxation modulus from the multiple-tau correlator (Green-Kubo form,
+ * Sec. 2.3): for level l and lag k, G[l][k] = mean over chains and over the
+ * components xy, yz, zx of <x(t) y(t - tau)>, x = sigma_ab, y = sigma_ab +
+ * sigma^v_ab, with the level-l series made of pairwise means of level l-1
+ * and tau = k 2^l sample_every dt.  G_dev, G_err_dev: [levels][16] FP64
+ * (G_err = batch-means standard error over corr_batches chain groups; 0 when
+ * corr_batches = 1); tau_host [levels][16]; counts_host [levels][16] int64
+ * number of products per chain and component (0 = no data, G = 0).  Chain
+ * sums are Neumaier-compensated.  Synchronises the stream. */
+int ssp_read_correlator(ssp_handle* h, double* G_dev, double* G_err_dev, double* tau_host, int64_t* counts_host,
+                        ssp_stream stream);
+
+/* Clears the correlator and the element series; the next sample is t = 0. */
+int ssp_reset_observables(ssp_handle* h, ssp_stream stream);
+
+/* Steps completed since ssp_init_equilibrium. */
+int ssp_step_count(const ssp_handle* h, int64_t* steps_host);
+
+/* The three standard normals the Euler move of step `step` draws for bead
+ * `bead` of the chain with global id `chain_id`, computed on the device in
+ * the handle's precision: out_dev [count][3] FP64 for beads bead..bead+count-1.
+ * Used to test the random streams in isolation. */
+int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead, int32_t count, double* out_dev,
+                    ssp_stream stream);
+
+/* Releases host resources (graphs, capture stream).  Caller memory untouched. */
+int ssp_destroy(ssp_handle* h);
+
+/* Message for the last error on h (NULL: last create/query error). */
+const char* ssp_last_error(const ssp_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSP_H */

@@ -1,0 +1,496 @@
+/*
+ * ssp_oracle.c -- plain FP64 CPU oracle for the single-chain slip-spring
+ * ensemble (Uneyama, "Single Chain Slip-Spring Model for Fast Rheology
+ * Simulations of Entangled Polymers on GPU").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file: it exists so that tests, the smoke check and the
+ * benchmark's CPU-baseline leg can check the HIP library against an
+ * independent, obviously-correct implementation.  It shares no code, header,
+ * table or constant generator with the HIP path.
+ *
+ * Everything is double precision, written as scalar loops in the order the
+ * paper states the method.  Units: b = kBT = zeta = 1 (Sec. 3.1), so the bond
+ * stiffness 3 kBT/b^2 is 3 and the slip-spring stiffness is 3/N_s.
+ *
+ * Indexing: beads i = 0..N-1 (the paper's 1..N), slip-spring slots
+ * j = 0..N-1.  A slot holds S_j in 0..N-1 when occupied and -1 when empty.
+ * Chain k occupies entries [off[k], off[k] + N[k]) of the bead arrays and of
+ * the slot arrays (slot capacity C = N, one slot per bead, Sec. 3.2).
+ * Positions are stored as xyz triples: R[3*(off+i)+a].
+ *
+ * Readings of the paper taken here (each is listed with its reason in the
+ * design notes of the repository):
+ *  - Euler step: R(t+dt) = R(t) + dt(-dJ/dR + kappa.R) + sqrt(2 dt) w, and
+ *    A(t+dt) = A(t) + dt kappa.A (the printed update drops the R(t), A(t)
+ *    terms; only this reading integrates the Langevin equation, Sec. 2.2).
+ *  - Hop (Sec. 3.1, substep 2): one uniform u per spring; S+1 if u < P+,
+ *    else S-1 if u < P+ + P-.  Positions used are the post-Langevin ones.
+ *  - Reconstruction (Sec. 3.1 substep 3 with K = C - Z attempts, Sec. 3.2):
+ *    every empty slot makes one attempt from the post-hop state with
+ *    p = min(dt/(zeta_s N0 K), 1/2) at bead 0 and p at bead N-1 (one
+ *    uniform: [0,p) -> bead 0, [p,2p) -> bead N-1).  Occupied slots sitting
+ *    on an end are destroyed with min(dt/zeta_s (delta_{S,0}+delta_{S,N-1}), 1).
+ *    A spring created in this step is not tested for destruction.
+ *  - Virtual stress sums over all Z springs (Appendix B form).
+ *  - Initial Z is drawn from Poisson(N/N0) truncated to 0..C.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11,
+ * "Parallel random numbers: as easy as 1, 2, 3"), implemented here from the
+ * published round function.  key = (seed_lo, seed_hi); counter =
+ * (index | purpose << 16, chain_id, step_lo, step_hi).  A 32-bit word w maps
+ * to u = ((w >> 9) + 0.5) * 2^-23 in (0,1); normals come from the
+ * Box-Muller transform r = sqrt(-2 ln u_a), theta = 2 pi u_b,
+ * (r cos theta, r sin theta).  Three normals per block: the pair from
+ * (w0,w1) and the cosine member of the pair from (w2,w3).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ---- Philox4x32-10, from the published definition ---------------------- */
+
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+enum {
+    P_INIT_BOND = 1,
+    P_INIT_Z = 2,
+    P_INIT_S = 3,
+    P_INIT_ANCHOR = 4,
+    P_NOISE = 5,
+    P_SLOT = 6,
+    P_ANCHOR = 7
+};
+
+void ssp_oracle_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(uint64_t seed, int purpose, int index, int64_t chain, int64_t step, uint32_t w[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = (uint32_t)index | ((uint32_t)purpose << 16);
+    ctr[1] = (uint32_t)chain;
+    ctr[2] = (uint32_t)((uint64_t)step & 0xffffffffu);
+    ctr[3] = (uint32_t)((uint64_t)step >> 32);
+    key[0] = (uint32_t)(seed & 0xffffffffu);
+    key[1] = (uint32_t)(seed >> 32);
+    ssp_oracle_philox(ctr, key, w);
+}
+
+double ssp_oracle_u01(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* Three standard normals from one Philox block. */
+static void normals3(const uint32_t w[4], double n[3])
+{
+    double r1 = sqrt(-2.0 * log(ssp_oracle_u01(w[0])));
+    double t1 = 2.0 * M_PI * ssp_oracle_u01(w[1]);
+    double r2 = sqrt(-2.0 * log(ssp_oracle_u01(w[2])));
+    double t2 = 2.0 * M_PI * ssp_oracle_u01(w[3]);
+    n[0] = r1 * cos(t1);
+    n[1] = r1 * sin(t1);
+    n[2] = r2 * cos(t2);
+}
+
+void ssp_oracle_normals3(uint64_t seed, int purpose, int index, int64_t chain, int64_t step, double n[3])
+{
+    uint32_t w[4];
+    draw(seed, purpose, index, chain, step, w);
+    normals3(w, n);
+}
+
+void ssp_oracle_block(uint64_t seed, int purpose, int index, int64_t chain, int64_t step, uint32_t w[4])
+{
+    draw(seed, purpose, index, chain, step, w);
+}
+
+/* ---- Initial equilibrium state (Sec. 3.1, sampling procedure) ------------ */
+
+/* P_eq(Z) is Poisson with mean N/N0 (Sec. 2.1); truncated to 0..C because a
+ * chain has only C slots (Sec. 3.2). */
+static int sample_truncated_poisson(double lambda, int cap, double u)
+{
+    double pmf = exp(-lambda);
+    double total = 0.0;
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)(cap + 1));
+    for (int z = 0; z <= cap; ++z) {
+        if (z > 0) pmf = pmf * lambda / (double)z;
+        total += pmf;
+        cdf[z] = total;
+    }
+    int result = cap;
+    for (int z = 0; z <= cap; ++z) {
+        if (u < cdf[z] / total) {
+            result = z;
+            break;
+        }
+    }
+    free(cdf);
+    return result;
+}
+
+void ssp_oracle_init(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
+                     double n0, double ns, uint64_t seed, double* R, double* A, int32_t* S)
+{
+    const double bond_sd = sqrt(1.0 / 3.0);   /* bond variance b^2/3 per component */
+    const double anchor_sd = sqrt(ns / 3.0);  /* anchor variance N_s b^2/3 per component */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < n_chains; ++k) {
+        const int n = N[k];
+        const int64_t o = off[k];
+        const int64_t c = chain_id[k];
+        double* r = R + 3 * o;
+        double* a = A + 3 * o;
+        int32_t* s = S + o;
+        /* 1. Gaussian chain: R_0 = 0, bonds N(0, 1/3). */
+        r[0] = r[1] = r[2] = 0.0;
+        for (int i = 0; i + 1 < n; ++i) {
+            double g[3];
+            ssp_oracle_normals3(seed, P_INIT_BOND, i, c, 0, g);
+            for (int d = 0; d < 3; ++d) r[3 * (i + 1) + d] = r[3 * i + d] + bond_sd * g[d];
+        }
+        /* 2. Z from the (truncated) Poisson distribution. */
+        uint32_t w[4];
+        draw(seed, P_INIT_Z, 0, c, 0, w);
+        int z = sample_truncated_poisson((double)n / n0, n, ssp_oracle_u01(w[0]));
+        /* 3. Slots 0..Z-1: S uniform on the beads, anchor Gaussian about R_S. */
+        for (int j = 0; j < n; ++j) {
+            if (j < z) {
+                draw(seed, P_INIT_S, j, c, 0, w);
+                int sj = (int)(((uint64_t)w[0] * (uint64_t)n) >> 32);
+                double g[3];
+                ssp_oracle_normals3(seed, P_INIT_ANCHOR, j, c, 0, g);
+                s[j] = sj;
+                for (int d = 0; d < 3; ++d) a[3 * j + d] = r[3 * sj + d] + anchor_sd * g[d];
+            } else {
+                s[j] = -1;
+                a[3 * j] = a[3 * j + 1] = a[3 * j + 2] = 0.0;
+            }
+        }
+    }
+}
+
+/* Discrete hop probability of a spring on bead i with anchor aj toward bead
+ * i + dir (dir = +1 or -1): min{(dt/zeta_s)[1 - tanh(3/(4 N_s) ((R_{i+dir} -
+ * A)^2 - (R_i - A)^2))], 1/2}, and 0 when i + dir leaves the chain (Sec. 3.1,
+ * substep 2, from the Glauber rates of Sec. 2.2). */
+double ssp_oracle_hop_prob(int n, const double* r, const double* aj, int i, int dir, double dt, double ns,
+                           double zeta_s)
+{
+    int t = i + dir;
+    if (t < 0 || t > n - 1) return 0.0;
+    double d0 = 0.0, d1 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double x0 = r[3 * i + d] - aj[d];
+        double x1 = r[3 * t + d] - aj[d];
+        d0 += x0 * x0;
+        d1 += x1 * x1;
+    }
+    double p = dt / zeta_s * (1.0 - tanh(3.0 / (4.0 * ns) * (d1 - d0)));
+    return p > 0.5 ? 0.5 : p;
+}
+
+/* ---- One time step (Sec. 3.1, three substeps) ---------------------------- */
+
+/* Event bits written per slot when an event array is given. */
+#define EV_HOP_UP 1
+#define EV_HOP_DOWN 2
+#define EV_DESTROY 4
+#define EV_CREATE_FIRST 8
+#define EV_CREATE_LAST 16
+
+/* Advances every chain by one step with step index `step` (the RNG counter).
+ * kappa: [n_chains][9] row-major velocity gradient per chain, (kappa.R)_a =
+ * sum_b kappa[a][b] R_b.  Optional outputs (may be NULL): events[slot] bits
+ * above; margin[slot] = smallest |u - threshold| over the decisions that slot
+ * took in this step (1.0 when it took none). */
+static void step_chain(int n, int64_t c, const double* kap, double dt, double n0, double ns, double zeta_s,
+                       uint64_t seed, int64_t step, double* r, double* a, int32_t* s, uint8_t* ev,
+                       double* margin, double* F, double* ro)
+{
+    const double kb = 3.0;
+    const double ks = 3.0 / ns;
+    const double sq2dt = sqrt(2.0 * dt);
+    const double anchor_sd = sqrt(ns / 3.0);
+    const double ch = dt / zeta_s;
+
+    if (ev)
+        for (int j = 0; j < n; ++j) ev[j] = 0;
+    if (margin)
+        for (int j = 0; j < n; ++j) margin[j] = 1.0;
+
+    /* Substep 1: forces F = -dJ/dR at time t (Eq. for the free energy, Sec. 2.1). */
+    for (int i = 0; i < 3 * n; ++i) F[i] = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+        for (int d = 0; d < 3; ++d) {
+            double b = r[3 * (i + 1) + d] - r[3 * i + d];
+            F[3 * i + d] += kb * b;
+            F[3 * (i + 1) + d] -= kb * b;
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        if (s[j] < 0) continue;
+        int i = s[j];
+        for (int d = 0; d < 3; ++d) F[3 * i + d] -= ks * (r[3 * i + d] - a[3 * j + d]);
+    }
+    /* Euler-Maruyama for beads; advection for occupied anchors. */
+    for (int i = 0; i < 3 * n; ++i) ro[i] = r[i];
+    for (int i = 0; i < n; ++i) {
+        double g[3];
+        ssp_oracle_normals3(seed, P_NOISE, i, c, step, g);
+        for (int d = 0; d < 3; ++d) {
+            double flow = kap[3 * d + 0] * ro[3 * i + 0] + kap[3 * d + 1] * ro[3 * i + 1] + kap[3 * d + 2] * ro[3 * i + 2];
+            r[3 * i + d] = ro[3 * i + d] + dt * (F[3 * i + d] + flow) + sq2dt * g[d];
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        if (s[j] < 0) continue;
+        double a0 = a[3 * j], a1 = a[3 * j + 1], a2 = a[3 * j + 2];
+        for (int d = 0; d < 3; ++d) {
+            double flow = kap[3 * d + 0] * a0 + kap[3 * d + 1] * a1 + kap[3 * d + 2] * a2;
+            a[3 * j + d] += dt * flow;
+        }
+    }
+
+    /* Substep 2: hops, all springs from the same post-Langevin positions. */
+    uint32_t w[4];
+    int32_t* s_after = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    for (int j = 0; j < n; ++j) {
+        s_after[j] = s[j];
+        if (s[j] < 0) continue;
+        int i = s[j];
+        double pp = ssp_oracle_hop_prob(n, r, a + 3 * j, i, +1, dt, ns, zeta_s);
+        double pm = ssp_oracle_hop_prob(n, r, a + 3 * j, i, -1, dt, ns, zeta_s);
+        draw(seed, P_SLOT, j, c, step, w);
+        double u = ssp_oracle_u01(w[0]);
+        if (u < pp) {
+            s_after[j] = i + 1;
+            if (ev) ev[j] |= EV_HOP_UP;
+        } else if (u < pp + pm) {
+            s_after[j] = i - 1;
+            if (ev) ev[j] |= EV_HOP_DOWN;
+        }
+        if (margin) {
+            double m = fabs(u - pp);
+            double m2 = fabs(u - (pp + pm));
+            if (m2 < m) m = m2;
+            if (m < margin[j]) margin[j] = m;
+        }
+    }
+    for (int j = 0; j < n; ++j) s[j] = s_after[j];
+    free(s_after);
+
+    /* Substep 3: reconstruction at the chain ends from the post-hop state. */
+    int z = 0;
+    for (int j = 0; j < n; ++j) z += (s[j] >= 0);
+    int kattempt = n - z;
+    double p = 0.0;
+    if (kattempt > 0) {
+        p = dt / (zeta_s * n0 * (double)kattempt);
+        if (p > 0.5) p = 0.5;
+    }
+    for (int j = 0; j < n; ++j) {
+        draw(seed, P_SLOT, j, c, step, w);
+        double u = ssp_oracle_u01(w[1]);
+        if (s[j] >= 0) {
+            int ends = (s[j] == 0) + (s[j] == n - 1);
+            if (ends == 0) continue;
+            double pd = ch * (double)ends;
+            if (pd > 1.0) pd = 1.0;
+            if (u < pd) {
+                s[j] = -1;
+                a[3 * j] = a[3 * j + 1] = a[3 * j + 2] = 0.0;
+                if (ev) ev[j] |= EV_DESTROY;
+            }
+            if (margin) {
+                double m = fabs(u - pd);
+                if (m < margin[j]) margin[j] = m;
+            }
+        } else {
+            int at = -1;
+            if (u < p) {
+                at = 0;
+                if (ev) ev[j] |= EV_CREATE_FIRST;
+            } else if (u < 2.0 * p) {
+                at = n - 1;
+                if (ev) ev[j] |= EV_CREATE_LAST;
+            }
+            if (margin) {
+                double m = fabs(u - p);
+                double m2 = fabs(u - 2.0 * p);
+                if (m2 < m) m = m2;
+                if (m < margin[j]) margin[j] = m;
+            }
+            if (at >= 0) {
+                double g[3];
+                ssp_oracle_normals3(seed, P_ANCHOR, j, c, step, g);
+                s[j] = at;
+                for (int d = 0; d < 3; ++d) a[3 * j + d] = r[3 * at + d] + anchor_sd * g[d];
+            }
+        }
+    }
+}
+
+/* Per-chain stress sigma (Eq. for the stress operator) and virtual stress
+ * sigma^v (Appendix B), 12 values: sigma xx yy zz xy yz zx, then sigma^v in the
+ * same order. */
+static void stress_chain(int n, double ns, const double* r, const double* a, const int32_t* s, double out[12])
+{
+    for (int q = 0; q < 12; ++q) out[q] = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+        double b[3];
+        for (int d = 0; d < 3; ++d) b[d] = r[3 * (i + 1) + d] - r[3 * i + d];
+        out[0] += 3.0 * b[0] * b[0];
+        out[1] += 3.0 * b[1] * b[1];
+        out[2] += 3.0 * b[2] * b[2];
+        out[3] += 3.0 * b[0] * b[1];
+        out[4] += 3.0 * b[1] * b[2];
+        out[5] += 3.0 * b[2] * b[0];
+    }
+    out[0] -= (double)n;
+    out[1] -= (double)n;
+    out[2] -= (double)n;
+    int z = 0;
+    for (int j = 0; j < n; ++j) {
+        if (s[j] < 0) continue;
+        ++z;
+        double d[3];
+        for (int e = 0; e < 3; ++e) d[e] = r[3 * s[j] + e] - a[3 * j + e];
+        double k = 3.0 / ns;
+        out[6] += k * d[0] * d[0];
+        out[7] += k * d[1] * d[1];
+        out[8] += k * d[2] * d[2];
+        out[9] += k * d[0] * d[1];
+        out[10] += k * d[1] * d[2];
+        out[11] += k * d[2] * d[0];
+    }
+    out[6] -= (double)z;
+    out[7] -= (double)z;
+    out[8] -= (double)z;
+}
+
+void ssp_oracle_stress(int n_chains, const int32_t* N, const int64_t* off, double ns, const double* R,
+                       const double* A, const int32_t* S, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n_chains; ++k) {
+        int64_t o = off[k];
+        stress_chain(N[k], ns, R + 3 * o, A + 3 * o, S + o, out + 12 * (int64_t)k);
+    }
+}
+
+/* One step for all chains.  events/margin may be NULL. */
+void ssp_oracle_step(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
+                     const double* kappa, double dt, double n0, double ns, double zeta_s, uint64_t seed,
+                     int64_t step, double* R, double* A, int32_t* S, uint8_t* events, double* margin)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int k = 0; k < n_chains; ++k) {
+        int n = N[k];
+        int64_t o = off[k];
+        double* F = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        double* ro = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        step_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, n0, ns, zeta_s, seed, step, R + 3 * o, A + 3 * o,
+                   S + o, events ? events + o : NULL, margin ? margin + o : NULL, F, ro);
+        free(F);
+        free(ro);
+    }
+}
+
+/* n_steps steps starting at step index step0, sampling the 12 stress values of
+ * every chain after each step whose 1-based count (step + 1) is a multiple of
+ * sample_every.  samples: [n_samples][n_chains][12] (may be NULL).  Returns
+ * the number of samples written. */
+int64_t ssp_oracle_run(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
+                       const double* kappa, double dt, double n0, double ns, double zeta_s, uint64_t seed,
+                       int64_t step0, int64_t n_steps, int64_t sample_every, double* R, double* A, int32_t* S,
+                       double* samples)
+{
+    int64_t n_samples = 0;
+    for (int64_t t = step0; t < step0 + n_steps; ++t)
+        if ((t + 1) % sample_every == 0) ++n_samples;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int k = 0; k < n_chains; ++k) {
+        int n = N[k];
+        int64_t o = off[k];
+        double* F = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        double* ro = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        int64_t q = 0;
+        for (int64_t t = step0; t < step0 + n_steps; ++t) {
+            step_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, n0, ns, zeta_s, seed, t, R + 3 * o, A + 3 * o,
+                       S + o, NULL, NULL, F, ro);
+            if ((t + 1) % sample_every == 0) {
+                if (samples) stress_chain(n, ns, R + 3 * o, A + 3 * o, S + o, samples + 12 * ((int64_t)n_chains * q + k));
+                ++q;
+            }
+        }
+        free(F);
+        free(ro);
+    }
+    return n_samples;
+}
+
+/* ---- Multiple-tau correlator, by its definition --------------------------
+ * Level 0 is the sample series itself; level l >= 1 is the series of
+ * pairwise means of consecutive, non-overlapping pairs of level l-1.  At
+ * every level, C[l][k] = sum_{n >= k} x_l[n] * y_l[n-k] and
+ * cnt[l][k] = max(0, len_l - k).  Lag k at level l stands for
+ * tau = k * 2^l sampling intervals.  x and y: [T] series of one quantity. */
+void ssp_oracle_multitau(int64_t T, const double* x, const double* y, int levels, int lags, double* C,
+                         int64_t* cnt)
+{
+    double* xl = (double*)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+    double* yl = (double*)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+    int64_t len = T;
+    for (int64_t n = 0; n < T; ++n) {
+        xl[n] = x[n];
+        yl[n] = y[n];
+    }
+    for (int l = 0; l < levels; ++l) {
+        if (l > 0) {
+            int64_t half = len / 2;
+            for (int64_t n = 0; n < half; ++n) {
+                xl[n] = (xl[2 * n] + xl[2 * n + 1]) * 0.5;
+                yl[n] = (yl[2 * n] + yl[2 * n + 1]) * 0.5;
+            }
+            len = half;
+        }
+        for (int k = 0; k < lags; ++k) {
+            double acc = 0.0;
+            for (int64_t n = k; n < len; ++n) acc += xl[n] * yl[n - k];
+            C[(int64_t)l * lags + k] = acc;
+            cnt[(int64_t)l * lags + k] = len > k ? len - k : 0;
+        }
+    }
+    free(xl);
+    free(yl);
+}

@@ -1,0 +1,466 @@
+"""Pins of the FP64 oracle to facts the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors and an independent library implementation (Philox),
+distribution laws (Box-Muller, the equilibrium sampler of Sec. 3.1),
+the free energy of Sec. 2.1 (forces by finite differences), the Glauber
+detailed-balance identity (Sec. 2.2), closed forms of the Euler-discretised
+Rouse chain (springs off), the exact stationary law of the N = 2 slot Markov
+chain (Sec. 3.1 substep 3 with K = C - Z, Sec. 3.2), and the linear-response
+prediction of Sec. 2.3 (step strain vs. the Green-Kubo correlation that
+includes the virtual stress).
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DT, N0, NS, ZS = 0.01, 4.0, 0.5, 0.1
+
+
+# ---------------------------------------------------------------- RNG ------
+
+def _kat_rows():
+    rows = []
+    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answer_vectors():
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        assert list(oracle.philox(ctr, key)) == want
+
+
+def test_philox_matches_rocrand_host_implementation():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    rng = np.random.default_rng(123)
+    cases = rng.integers(0, 2**32, size=(200, 6), dtype=np.uint64)
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "rr")
+        subprocess.check_call([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-o", exe,
+                               os.path.join(HERE, "rocrand_philox_ref.cpp")], cwd=d)
+        inp = "\n".join(" ".join(str(int(x)) for x in row) for row in cases) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for row, line in zip(cases, out):
+        want = [int(x) for x in line.split()]
+        got = list(oracle.philox(row[:4], row[4:6]))
+        assert got == want
+
+
+def test_u01_grid_and_range():
+    assert oracle.u01(0) == 0.5 * 2.0**-23
+    assert oracle.u01(0xFFFFFFFF) == 1.0 - 0.5 * 2.0**-23
+    assert oracle.u01(1 << 9) == 1.5 * 2.0**-23
+    # exactly representable in binary32: (2k+1) < 2^24
+    for w in [0, 1 << 9, 12345 << 9, 0xFFFFFFFF]:
+        u = oracle.u01(w)
+        assert float(np.float32(u)) == u
+
+
+def test_box_muller_normals_are_standard():
+    g = np.array([oracle.normals3(7, oracle.P_NOISE, i % 64, i // 64, 3) for i in range(60000)])
+    assert np.all(np.isfinite(g))
+    for c in range(3):
+        x = g[:, c]
+        assert abs(x.mean()) < 4.0 / math.sqrt(len(x))
+        assert abs(x.var() - 1.0) < 4.0 * math.sqrt(2.0 / len(x))
+        assert stats.kstest(x, "norm").pvalue > 1e-3
+    # the three components are uncorrelated
+    cc = np.corrcoef(g.T)
+    assert np.max(np.abs(cc - np.eye(3))) < 4.0 / math.sqrt(len(g))
+
+
+def test_streams_are_distinct_by_purpose_chain_step():
+    a = oracle.block(1, oracle.P_NOISE, 3, 5, 7)
+    assert not np.array_equal(a, oracle.block(1, oracle.P_SLOT, 3, 5, 7))
+    assert not np.array_equal(a, oracle.block(1, oracle.P_NOISE, 3, 6, 7))
+    assert not np.array_equal(a, oracle.block(1, oracle.P_NOISE, 3, 5, 8))
+    assert not np.array_equal(a, oracle.block(2, oracle.P_NOISE, 3, 5, 7))
+    # step counter uses both 32-bit halves
+    assert not np.array_equal(oracle.block(1, oracle.P_NOISE, 0, 0, 1), oracle.block(1, oracle.P_NOISE, 0, 0, 1 << 32))
+
+
+# -------------------------------------------------------- initial state ----
+
+def test_equilibrium_sampler_laws():
+    """Sec. 3.1 sampling procedure; laws of Sec. 2.1 (ideal chain bonds,
+    Poisson Z, uniform S, Gaussian anchors)."""
+    M, N = 20000, 8
+    e = oracle.Ensemble([N] * M, seed=11).init()
+    R = e.R.reshape(M, N, 3)
+    assert np.all(R[:, 0, :] == 0.0)
+    b = (R[:, 1:] - R[:, :-1]).ravel()
+    assert stats.kstest(b / math.sqrt(1.0 / 3.0), "norm").pvalue > 1e-3
+    S = e.S.reshape(M, N)
+    Z = (S >= 0).sum(axis=1)
+    # occupied slots are exactly 0..Z-1
+    for k in range(0, M, 997):
+        assert np.all(S[k, :Z[k]] >= 0) and np.all(S[k, Z[k]:] == -1)
+    lam = N / N0
+    pmf = np.array([math.exp(-lam) * lam**z / math.factorial(z) for z in range(N + 1)])
+    pmf /= pmf.sum()
+    obs = np.bincount(Z, minlength=N + 1)
+    exp = pmf * M
+    keep = exp > 5
+    chi2 = (((obs - exp) ** 2 / exp)[keep]).sum()
+    assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-3
+    s = S[S >= 0]
+    cnt = np.bincount(s, minlength=N)
+    chi2 = ((cnt - len(s) / N) ** 2 / (len(s) / N)).sum()
+    assert stats.chi2.sf(chi2, N - 1) > 1e-3
+    d = e.anchor_offsets()
+    d = d[~np.isnan(d[:, 0])].ravel()
+    assert stats.kstest(d / math.sqrt(NS / 3.0), "norm").pvalue > 1e-3
+
+
+# ------------------------------------------------------- forces / flow -----
+
+def _free_energy(R, A, S, ns):
+    f = 1.5 * np.sum((R[1:] - R[:-1]) ** 2)
+    for j, s in enumerate(S):
+        if s >= 0:
+            f += 1.5 / ns * np.sum((R[s] - A[j]) ** 2)
+    return f
+
+
+def _set_state(e, R, A, S):
+    e.R[:] = R
+    e.A[:] = A
+    e.S[:] = S
+
+
+def test_force_is_minus_gradient_of_free_energy():
+    """Substep 1 drift equals -dF/dR (Sec. 2.1 free energy, Sec. 3.1)."""
+    rng = np.random.default_rng(5)
+    N = 6
+    e = oracle.Ensemble([N], seed=3, n0=1e30)  # no creation: p = 0
+    R = rng.normal(size=(N, 3))
+    A = rng.normal(size=(N, 3))
+    S = np.array([2, 2, -1, 0, 5, 3], dtype=np.int32)  # two springs share bead 2
+    _set_state(e, R, A, S)
+    e.step_index = 17
+    e.step()
+    g = np.array([oracle.normals3(3, oracle.P_NOISE, i, 0, 17) for i in range(N)])
+    drift = (e.R - R - math.sqrt(2 * DT) * g) / DT
+    h = 1e-5
+    grad = np.zeros_like(R)
+    for i in range(N):
+        for c in range(3):
+            Rp, Rm = R.copy(), R.copy()
+            Rp[i, c] += h
+            Rm[i, c] -= h
+            grad[i, c] = (_free_energy(Rp, A, S, NS) - _free_energy(Rm, A, S, NS)) / (2 * h)
+    np.testing.assert_allclose(drift, -grad, rtol=1e-7, atol=1e-7)
+
+
+def test_flow_term_orientation_and_anchor_advection():
+    """kappa.R with (kappa.R)_a = sum_b kappa_ab R_b; simple shear
+    kappa_xy = gdot moves x by gdot*y (Sec. 2.2 and the shear flow of
+    Sec. 4.1); anchors are advected affinely."""
+    rng = np.random.default_rng(8)
+    N = 4
+    R = rng.normal(size=(N, 3))
+    A = rng.normal(size=(N, 3))
+    S = np.array([1, -1, 3, -1], dtype=np.int32)
+    kap = np.zeros((3, 3))
+    kap[0, 1] = 0.7
+    out = {}
+    for name, k in [("flow", kap), ("rest", np.zeros((3, 3)))]:
+        e = oracle.Ensemble([N], seed=4, n0=1e30, zeta_s=1e30)  # no hops, no reconstruction
+        _set_state(e, R, A, S)
+        e.step(k)
+        out[name] = (e.R.copy(), e.A.copy())
+    np.testing.assert_allclose(out["flow"][0] - out["rest"][0], DT * R @ kap.T, rtol=1e-12, atol=1e-14)
+    dA = out["flow"][1] - A
+    np.testing.assert_allclose(dA[[0, 2]], DT * A[[0, 2]] @ kap.T, rtol=1e-12, atol=1e-14)
+
+
+def test_hop_detailed_balance_glauber():
+    """P(S->S+1) exp(-F(S)) = P(S+1->S) exp(-F(S+1)) for the unclipped
+    Glauber probabilities (Sec. 2.2 rates; Sec. 3.1 substep 2)."""
+    rng = np.random.default_rng(9)
+    N = 7
+    for trial in range(20):
+        R = rng.normal(size=(N, 3)) * 0.8
+        a = rng.normal(size=3) * 0.5
+        for s in range(N - 1):
+            pu = oracle.hop_prob(R, a, s, +1, DT, NS, ZS)
+            pd = oracle.hop_prob(R, a, s + 1, -1, DT, NS, ZS)
+            F0 = 1.5 / NS * np.sum((R[s] - a) ** 2)
+            F1 = 1.5 / NS * np.sum((R[s + 1] - a) ** 2)
+            assert pu < 0.5 and pd < 0.5
+            assert pu * math.exp(-F0) == pytest.approx(pd * math.exp(-F1), rel=1e-12)
+        assert oracle.hop_prob(R, a, N - 1, +1, DT, NS, ZS) == 0.0
+        assert oracle.hop_prob(R, a, 0, -1, DT, NS, ZS) == 0.0
+    # zero energy difference: (dt/zeta_s)(1 - tanh 0) = dt/zeta_s
+    R = np.zeros((3, 3))
+    assert oracle.hop_prob(R, np.zeros(3), 1, +1, DT, NS, ZS) == pytest.approx(DT / ZS, rel=1e-15)
+    # the 1/2 cap binds for large dt/zeta_s
+    assert oracle.hop_prob(R, np.zeros(3), 1, +1, 0.4, NS, 0.1) == 0.5
+
+
+# ------------------------------------------- discrete Rouse closed forms ---
+
+def _rouse_modes(N, dt):
+    p = np.arange(1, N)
+    lam = 4.0 * np.sin(p * np.pi / (2 * N)) ** 2
+    return lam, 1.0 - 3.0 * dt * lam
+
+
+def rouse_corr(N, dt, n):
+    """<sigma_xy(n dt) sigma_xy(0)> of the Euler-discretised Rouse chain in its
+    stationary state: sum_p rho_p^(2n) / (1 - 1.5 dt lam_p)^2."""
+    lam, rho = _rouse_modes(N, dt)
+    return float(np.sum(rho ** (2 * n) / (1.0 - 1.5 * dt * lam) ** 2))
+
+
+def rouse_normal(N, dt):
+    lam, _ = _rouse_modes(N, dt)
+    return float(np.sum(1.0 / (1.0 - 1.5 * dt * lam)) - N)
+
+
+def _rouse_lyapunov(N, dt, lags):
+    """The same stationary quantities by a different route: solve the discrete
+    Lyapunov equation Sigma = M Sigma M^T + 2 dt B for the bond covariance of
+    b' = M b + sqrt(2 dt) D w (B = D D^T, M = 1 - 3 dt B)."""
+    import scipy.linalg as sl
+    D = np.zeros((N - 1, N))
+    for i in range(N - 1):
+        D[i, i], D[i, i + 1] = -1.0, 1.0
+    B = D @ D.T
+    Mm = np.eye(N - 1) - 3.0 * dt * B
+    Sig = sl.solve_discrete_lyapunov(Mm, 2.0 * dt * B)
+    corr = [9.0 * float(np.sum((np.linalg.matrix_power(Mm, n) @ Sig) ** 2)) for n in lags]
+    return 3.0 * float(np.trace(Sig)) - N, corr
+
+
+def test_rouse_closed_forms_agree_with_lyapunov_solution():
+    for N in (4, 8, 16):
+        normal, corr = _rouse_lyapunov(N, DT, [0, 5, 100])
+        assert rouse_normal(N, DT) == pytest.approx(normal, rel=1e-12)
+        for n, c in zip([0, 5, 100], corr):
+            assert rouse_corr(N, DT, n) == pytest.approx(c, rel=1e-10)
+
+
+def _batch_se(per_chain, nb=32):
+    b = np.array([x.mean() for x in np.array_split(per_chain, nb)])
+    return b.mean(), b.std(ddof=1) / math.sqrt(nb)
+
+
+@pytest.fixture(scope="module")
+def rouse_run():
+    N, M = 8, 1024
+    e = oracle.Ensemble([N] * M, seed=21, n0=1e30).init()  # springs switched off
+    e.run(600, keep_samples=False)                          # relax to the discrete stationary law
+    s = e.run(4000, sample_every=5)                         # [800][M][12]
+    return N, s
+
+
+@pytest.mark.parametrize("lag_samples", [0, 1, 4, 10, 20])
+def test_rouse_stress_autocorrelation_closed_form(rouse_run, lag_samples):
+    N, s = rouse_run
+    T = s.shape[0]
+    off = s[:, :, 3:6]  # xy yz zx
+    prod = (off[lag_samples:] * off[:T - lag_samples]).mean(axis=(0, 2))  # per chain
+    est, se = _batch_se(prod)
+    want = rouse_corr(N, DT, 5 * lag_samples)
+    assert abs(est - want) < 4.0 * se + 1e-12, (est, want, se)
+    if lag_samples == 0:
+        # the discrete map differs from the continuous Rouse value N - 1
+        assert abs(est - (N - 1)) > 4.0 * se
+
+
+def test_rouse_mean_normal_stress_closed_form(rouse_run):
+    N, s = rouse_run
+    per_chain = s[:, :, 0:3].mean(axis=(0, 2))
+    est, se = _batch_se(per_chain)
+    want = rouse_normal(N, DT)
+    assert want == pytest.approx(-0.7805449, abs=1e-6)
+    assert abs(est - want) < 4.0 * se
+    assert abs(est - (-1.0)) > 4.0 * se  # continuous equilibrium value -kBT
+
+
+# ------------------------------------------ N = 2: exact slot Markov chain ---
+
+def n2_stationary(dt=DT, n0=N0, zeta_s=ZS):
+    """Z of a 2-bead chain is an autonomous Markov chain (both beads are ends):
+    each occupied slot is destroyed with min(dt/zeta_s, 1); each of the
+    K = 2 - Z empty slots creates with probability 2 min(dt/(zeta_s n0 K), 1/2);
+    springs created in the step are not destroyed in it."""
+    from math import comb
+    cd = min(dt / zeta_s, 1.0)
+    P = np.zeros((3, 3))
+    for z in range(3):
+        K = 2 - z
+        q = 2.0 * min(dt / (zeta_s * n0 * K), 0.5) if K > 0 else 0.0
+        for d in range(z + 1):
+            pd = comb(z, d) * cd**d * (1 - cd) ** (z - d)
+            for c in range(K + 1):
+                pc = comb(K, c) * q**c * (1 - q) ** (K - c)
+                P[z, z - d + c] += pd * pc
+    w, v = np.linalg.eig(P.T)
+    pi = np.real(v[:, np.argmin(np.abs(w - 1))])
+    return pi / pi.sum()
+
+
+def test_n2_stationary_law_of_z():
+    pi = n2_stationary()
+    np.testing.assert_allclose(pi, [0.613472, 0.310881, 0.075648], atol=2e-6)
+    M = 20000
+    e = oracle.Ensemble([2] * M, seed=31).init()
+    e.run(300, keep_samples=False)
+    Zt = []
+    for _ in range(60):
+        e.run(25, keep_samples=False)
+        Zt.append((e.S.reshape(M, 2) >= 0).sum(axis=1))
+    Zt = np.array(Zt)  # [60][M]
+    frac = np.stack([(Zt == z).mean(axis=0) for z in range(3)], axis=1)  # per chain
+    for z in range(3):
+        est, se = _batch_se(frac[:, z])
+        assert abs(est - pi[z]) < 4.0 * se + 1e-4, (z, est, pi[z], se)
+
+
+# ---------------------------------------- equilibrium with springs on ------
+
+def test_springs_on_equilibrium_laws_small_dt_bias():
+    """With springs on, the stationary state of the scheme approaches the
+    equilibrium of Sec. 2.1 (Poisson Z of mean N/N0, uniform S, anchor
+    offsets of variance N_s/3, bonds of variance 1/3) up to O(dt)."""
+    N, M = 8, 4096
+    e = oracle.Ensemble([N] * M, seed=41).init()
+    e.run(1500, keep_samples=False)
+    S = e.S.reshape(M, N)
+    Z = (S >= 0).sum(axis=1)
+    assert Z.mean() == pytest.approx(N / N0, rel=0.03)
+    cnt = np.bincount(S[S >= 0], minlength=N) / (S >= 0).sum()
+    np.testing.assert_allclose(cnt, 1.0 / N, atol=0.02)
+    d = e.anchor_offsets()
+    d = d[~np.isnan(d[:, 0])]
+    assert d.var() == pytest.approx(NS / 3.0, rel=0.06)
+    R = e.R.reshape(M, N, 3)
+    assert (R[:, 1:] - R[:, :-1]).var() == pytest.approx(1.0 / 3.0, rel=0.06)
+
+
+# --------------------------------------------- linear response (Sec. 2.3) ----
+
+def test_step_strain_response_equals_green_kubo_with_virtual_stress():
+    """The mean shear stress after a small step strain gamma, divided by gamma,
+    equals <sigma_xy(t) [sigma_xy(0) + sigma^v_xy(0)]> (Green-Kubo form with the
+    virtual stress, Sec. 2.3), not the plain stress autocorrelation alone.
+    The strained and reference ensembles share their random streams (common
+    random numbers); sigma_xy is odd in gamma, so the nonlinear error is
+    O(gamma^3)."""
+    N, M, gamma, T, TB = 8, 16384, 0.1, 120, 400
+    kap = np.zeros((3, 3))
+    kap[0, 1] = gamma / DT
+    base = oracle.Ensemble([N] * M, seed=51).init()
+    strained = oracle.Ensemble([N] * M, seed=51).init()
+    s0 = base.stress()
+    sb = np.concatenate([s0[None], base.run(TB, sample_every=1)], axis=0)  # sb[t] after t steps
+    strained.step(kap)
+    ss = np.concatenate([strained.stress()[None], strained.run(T - 1, sample_every=1)], axis=0)  # ss[t]: t+1 steps
+    resp = (ss[:, :, 3] - sb[1:T + 1, :, 3]) / gamma
+    x = sb[:, :, 3]
+    y = sb[:, :, 3] + sb[:, :, 9]
+
+    def gk(L, yy):
+        per_chain = (x[L:] * yy[:TB + 1 - L]).mean(axis=0)
+        return _batch_se(per_chain)
+
+    results = []
+    for L in [20, 40, 80, 119]:
+        r_est, r_se = _batch_se(resp[L])
+        g_full, g_se = gk(L + 1, y)   # response after L+1 steps of evolution
+        g_plain, gp_se = gk(L + 1, x)
+        results.append((L, r_est, g_full, g_plain))
+        tol = 4.0 * math.hypot(r_se, g_se)
+        assert abs(r_est - g_full) < tol + 0.02 * abs(g_full), (L, r_est, r_se, g_full, g_se, g_plain)
+    # the virtual-stress term is needed: the plain autocorrelation misses the
+    # response by many standard errors at the longer lags
+    L = 119
+    r_est, r_se = _batch_se(resp[L])
+    g_plain, gp_se = gk(L + 1, x)
+    assert abs(r_est - g_plain) > 4.0 * math.hypot(r_se, gp_se), results
+
+
+# -------------------------------------------------- multiple-tau correlator --
+
+def test_multitau_constant_and_alternating_series():
+    T = 1000
+    C, cnt = oracle.multitau(np.full(T, 2.0), np.full(T, 3.0), levels=6, lags=16)
+    ok = cnt > 0
+    np.testing.assert_allclose(C[ok] / cnt[ok], 6.0, rtol=1e-14)
+    x = (-1.0) ** np.arange(T)
+    C, cnt = oracle.multitau(x, x, levels=4, lags=16)
+    np.testing.assert_allclose(C[0] / cnt[0], (-1.0) ** np.arange(16), rtol=1e-14)
+    assert np.all(C[1:] == 0.0)
+    assert cnt[0, 0] == T and cnt[0, 15] == T - 15 and cnt[1, 0] == T // 2 and cnt[3, 3] == T // 8 - 3
+
+
+def test_multitau_equals_block_mean_brute_force():
+    rng = np.random.default_rng(2)
+    T = 777
+    x, y = rng.normal(size=T), rng.normal(size=T)
+    C, cnt = oracle.multitau(x, y, levels=5, lags=16)
+    for lvl in range(5):
+        b = 2**lvl
+        nb = T // b
+        # level l of the pairwise-mean hierarchy has len_{l} = floor(len_{l-1}/2);
+        # for these sizes it equals floor(T / 2^l)
+        xb = x[: nb * b].reshape(nb, b).mean(axis=1)
+        yb = y[: nb * b].reshape(nb, b).mean(axis=1)
+        for k in range(16):
+            want = float(np.dot(xb[k:], yb[: nb - k])) if nb > k else 0.0
+            assert C[lvl, k] == pytest.approx(want, rel=1e-12, abs=1e-12)
+            assert cnt[lvl, k] == max(0, nb - k)
+
+
+# ------------------------------------------------------- structural facts ---
+
+def test_run_equals_repeated_step_and_sharding_invariance():
+    N = [5, 9, 12]
+    a = oracle.Ensemble(N, seed=61).init()
+    b = oracle.Ensemble(N, seed=61).init()
+    kap = np.zeros((3, 3))
+    kap[0, 1] = 0.3
+    a.run(40, kappa=kap, keep_samples=False)
+    for _ in range(40):
+        b.step(kap)
+    assert np.array_equal(a.R, b.R) and np.array_equal(a.A, b.A) and np.array_equal(a.S, b.S)
+    # a chain's trajectory depends only on its global id, not on its neighbours
+    c = oracle.Ensemble([12], chain_ids=[2], seed=61).init()
+    c.run(40, kappa=kap, keep_samples=False)
+    o = a.off[2]
+    assert np.array_equal(c.R, a.R[o:o + 12]) and np.array_equal(c.S, a.S[o:o + 12])
+
+
+def test_reconstruction_only_at_ends_and_capacity():
+    e = oracle.Ensemble([6] * 500, seed=71).init()
+    prev = e.S.copy()
+    for _ in range(200):
+        ev, _ = e.step(want_events=True)
+        created = (ev & (oracle.EV_CREATE_FIRST | oracle.EV_CREATE_LAST)) != 0
+        destroyed = (ev & oracle.EV_DESTROY) != 0
+        assert np.all(prev[created] == -1)
+        pos = e.S[created]
+        assert np.all((pos == 0) | (pos == 5))
+        assert np.all(e.S[destroyed] == -1)
+        prev = e.S.copy()
+    assert np.all(e.S < 6)
