@@ -1,0 +1,116 @@
+"""ctypes declarations of the libssp C ABI (include/ssp.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libssp.so")
+
+SSP_OK = 0
+SSP_EINVAL = -1
+SSP_ESIZE = -2
+SSP_EHIP = -3
+SSP_ENONFINITE = -4
+SSP_ESTATE = -5
+SSP_FP32 = 0
+SSP_FP64 = 1
+SSP_MAX_BEADS = 128
+
+EXPORTS = [
+    "ssp_config_init",
+    "ssp_query_sizes",
+    "ssp_create",
+    "ssp_init_equilibrium",
+    "ssp_step",
+    "ssp_read_stress",
+    "ssp_read_state",
+    "ssp_write_state",
+    "ssp_read_element_series",
+    "ssp_read_correlator",
+    "ssp_reset_observables",
+    "ssp_step_count",
+    "ssp_rng_normals",
+    "ssp_destroy",
+    "ssp_last_error",
+]
+
+
+class SspConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_chains", ctypes.c_int64),
+        ("n_elements", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("n_beads_host", ctypes.POINTER(ctypes.c_int32)),
+        ("n_beads", ctypes.c_int32),
+        ("sample_every", ctypes.c_int32),
+        ("element_offsets_host", ctypes.POINTER(ctypes.c_int32)),
+        ("chain_ids_host", ctypes.POINTER(ctypes.c_int64)),
+        ("dt", ctypes.c_double),
+        ("n0", ctypes.c_double),
+        ("ns", ctypes.c_double),
+        ("zeta_s", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("max_steps_per_launch", ctypes.c_int32),
+        ("corr_levels", ctypes.c_int32),
+        ("corr_lags", ctypes.c_int32),
+        ("corr_batches", ctypes.c_int32),
+        ("series_capacity", ctypes.c_int64),
+        ("use_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class SspError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libssp error {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libssp (raises if it is not built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libssp.so not found at {LIB_PATH}; build it with `python -m paper_1106_2899_amd.build`"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f64p = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        cfgp = ctypes.POINTER(SspConfig)
+        sig = {
+            "ssp_config_init": [cfgp],
+            "ssp_query_sizes": [cfgp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+            "ssp_create": [cfgp, vp, vp, ctypes.POINTER(vp)],
+            "ssp_init_equilibrium": [vp, vp],
+            "ssp_step": [vp, i64, vp, vp],
+            "ssp_read_stress": [vp, vp, vp],
+            "ssp_read_state": [vp, vp, vp, vp, vp],
+            "ssp_write_state": [vp, vp, vp, vp, vp],
+            "ssp_read_element_series": [vp, vp, ctypes.POINTER(ctypes.c_int64), vp],
+            "ssp_read_correlator": [vp, vp, vp, f64p, ctypes.POINTER(ctypes.c_int64), vp],
+            "ssp_reset_observables": [vp, vp],
+            "ssp_step_count": [vp, ctypes.POINTER(ctypes.c_int64)],
+            "ssp_rng_normals": [vp, i64, i64, i32, i32, vp, vp],
+            "ssp_destroy": [vp],
+            "ssp_last_error": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "ssp_last_error" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc: int, handle=None) -> None:
+    if rc != SSP_OK:
+        msg = lib().ssp_last_error(handle)
+        raise SspError(rc, msg.decode() if msg else "")

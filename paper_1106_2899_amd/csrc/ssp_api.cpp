@@ -1,0 +1,669 @@
+// Host side of libssp: configuration checks, device memory layout inside the
+// caller's buffers, launch sequencing, hipGraph capture/replay, and the
+// extern "C" entry points declared in include/ssp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ssp.h"
+#include "ssp_internal.h"
+
+using namespace ssp;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Chain-to-wavefront mapping of one group of chains: segment width W lanes
+// and B beads per lane, W * B >= N for every chain of the group.
+struct Mapping {
+    int W, B;
+    bool operator<(const Mapping& o) const { return W != o.W ? W < o.W : B < o.B; }
+};
+
+Mapping default_mapping(int n)
+{
+    if (n <= 8) return {8, 1};
+    if (n <= 16) return {16, 1};
+    if (n <= 32) return {32, 1};
+    if (n <= 64) return {64, 1};
+    return {64, 2};
+}
+
+struct Layout {
+    // work buffer offsets (bytes)
+    size_t ctrl, flags, off, n, elem, gid, tasks, elem_off, thr, samples, hist, acc, pend, batch, series, corr_out,
+        total;
+    // state buffer offsets
+    size_t r0, r1, a0, a1, s, state_total;
+    int64_t q_cap;
+    int32_t chunk;
+};
+
+struct Resolved {
+    ssp_config cfg;
+    std::vector<int32_t> N;
+    std::vector<int32_t> elem_off;
+    std::vector<int64_t> ids;
+    int64_t total_beads = 0;
+};
+
+bool resolve(const ssp_config* c, Resolved& r, std::string& err)
+{
+    if (!c) {
+        err = "null config";
+        return false;
+    }
+    r.cfg = *c;
+    const ssp_config& k = r.cfg;
+    if (k.n_chains < 1) {
+        err = "n_chains must be >= 1";
+        return false;
+    }
+    if (k.n_chains > (int64_t)INT32_MAX) {
+        err = "n_chains must fit in int32";
+        return false;
+    }
+    if (k.n_elements < 1 || k.n_elements > k.n_chains) {
+        err = "n_elements must be in 1..n_chains";
+        return false;
+    }
+    if (k.precision != SSP_FP32 && k.precision != SSP_FP64) {
+        err = "precision must be SSP_FP32 or SSP_FP64";
+        return false;
+    }
+    if (!(k.dt > 0.0) || !(k.n0 > 0.0) || !(k.ns > 0.0) || !(k.zeta_s > 0.0) || !std::isfinite(k.dt) ||
+        !std::isfinite(k.ns) || !std::isfinite(k.zeta_s)) {
+        err = "dt, n0, ns and zeta_s must be positive and finite";
+        return false;
+    }
+    if (k.sample_every < 1) {
+        err = "sample_every must be >= 1";
+        return false;
+    }
+    if (k.corr_levels < 0 || k.corr_levels > kMaxCorrLevels) {
+        err = "corr_levels must be in 0..16";
+        return false;
+    }
+    if (k.corr_levels > 0 && k.corr_lags != kCorrLags) {
+        err = "corr_lags must be 16";
+        return false;
+    }
+    if (k.corr_levels > 0 && (k.corr_batches < 1 || k.corr_batches > 64 || k.corr_batches > k.n_chains)) {
+        err = "corr_batches must be in 1..min(64, n_chains)";
+        return false;
+    }
+    if (k.series_capacity < 0) {
+        err = "series_capacity must be >= 0";
+        return false;
+    }
+    if (k.max_steps_per_launch < 0) {
+        err = "max_steps_per_launch must be >= 0";
+        return false;
+    }
+    const int64_t M = k.n_chains;
+    r.N.resize(M);
+    for (int64_t i = 0; i < M; ++i) {
+        const int32_t n = k.n_beads_host ? k.n_beads_host[i] : k.n_beads;
+        if (n < 2 || n > SSP_MAX_BEADS) {
+            err = "every chain needs 2 <= N <= 128 beads (chain " + std::to_string(i) + ")";
+            return false;
+        }
+        r.N[i] = n;
+        r.total_beads += n;
+    }
+    r.elem_off.resize(k.n_elements + 1);
+    if (k.element_offsets_host) {
+        for (int e = 0; e <= k.n_elements; ++e) r.elem_off[e] = k.element_offsets_host[e];
+        if (r.elem_off[0] != 0 || r.elem_off[k.n_elements] != M) {
+            err = "element_offsets must start at 0 and end at n_chains";
+            return false;
+        }
+        for (int e = 0; e < k.n_elements; ++e)
+            if (r.elem_off[e + 1] <= r.elem_off[e]) {
+                err = "element_offsets must be strictly increasing";
+                return false;
+            }
+    } else {
+        for (int e = 0; e <= k.n_elements; ++e) r.elem_off[e] = (int32_t)(M * e / k.n_elements);
+        for (int e = 0; e < k.n_elements; ++e)
+            if (r.elem_off[e + 1] <= r.elem_off[e]) {
+                err = "empty element in equal split";
+                return false;
+            }
+    }
+    r.ids.resize(M);
+    for (int64_t i = 0; i < M; ++i) {
+        r.ids[i] = k.chain_ids_host ? k.chain_ids_host[i] : i;
+        if (r.ids[i] < 0 || r.ids[i] > (int64_t)UINT32_MAX) {
+            err = "chain ids must be in 0..2^32-1";
+            return false;
+        }
+    }
+    return true;
+}
+
+Layout make_layout(const Resolved& r)
+{
+    const ssp_config& k = r.cfg;
+    const int64_t M = k.n_chains;
+    Layout L{};
+    // steps per launch: bounded so that the per-launch sample buffer stays below
+    // about 1 GiB (12 FP64 values per chain and sample).
+    int32_t chunk = k.max_steps_per_launch;
+    if (chunk == 0) {
+        const double per_sample = (double)M * kSampleValues * 8.0;
+        int64_t max_q = (int64_t)std::max(1.0, std::floor((1024.0 * 1024.0 * 1024.0) / per_sample));
+        int64_t c = std::min<int64_t>(1000, max_q * k.sample_every);
+        chunk = (int32_t)std::max<int64_t>(1, c);
+    }
+    L.chunk = chunk;
+    L.q_cap = chunk / k.sample_every + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.ctrl = take(sizeof(int64_t) * kCtrlWords);
+    L.flags = take(sizeof(uint32_t));
+    L.off = take(sizeof(int64_t) * M);
+    L.n = take(sizeof(int32_t) * M);
+    L.elem = take(sizeof(int32_t) * M);
+    L.gid = take(sizeof(uint32_t) * M);
+    L.tasks = take(sizeof(int32_t) * M);
+    L.elem_off = take(sizeof(int32_t) * (k.n_elements + 1));
+    L.thr = take(sizeof(uint32_t) * 2 * (kMaxBeads + 1));
+    L.samples = take(sizeof(double) * (size_t)L.q_cap * M * kSampleValues);
+    const int lv = k.corr_levels;
+    L.hist = take(lv ? sizeof(double) * (size_t)lv * 3 * M * 16 : 0);
+    L.acc = take(lv ? sizeof(double) * (size_t)lv * 3 * M * 16 : 0);
+    L.pend = take(lv ? sizeof(double) * (size_t)3 * M * 16 * 2 : 0);
+    L.batch = take(lv ? sizeof(double) * (size_t)k.corr_batches * lv * 16 : 0);
+    L.corr_out = take(lv ? sizeof(double) * (size_t)lv * 16 * 2 : 0);
+    L.series = take(sizeof(double) * (size_t)k.n_elements * k.series_capacity * 6);
+    L.total = o;
+    const size_t beads = (size_t)r.total_beads;
+    const size_t v4 = k.precision == SSP_FP32 ? 16 : 32;
+    o = 0;
+    L.r0 = take(v4 * beads);
+    L.r1 = k.precision == SSP_FP32 ? take(v4 * beads) : 0;
+    L.a0 = take(v4 * beads);
+    L.a1 = k.precision == SSP_FP32 ? take(v4 * beads) : 0;
+    L.s = take(sizeof(int32_t) * beads);
+    L.state_total = o;
+    return L;
+}
+
+// Integer form of u < p for u = ((w >> 9) + 1/2) 2^-23: (w >> 9) < ceil(p 2^23 - 1/2).
+uint32_t threshold(double p)
+{
+    const double x = std::ceil(p * 8388608.0 - 0.5);
+    if (x <= 0.0) return 0u;
+    if (x >= 8388608.0) return 8388608u;
+    return (uint32_t)x;
+}
+
+}  // namespace
+
+struct ssp_handle {
+    Resolved res;
+    Layout lay;
+    int device = 0;
+    char* state = nullptr;
+    char* work = nullptr;
+    std::vector<std::pair<Mapping, std::pair<int64_t, int64_t>>> groups;  // mapping, [task begin, count)
+    bool initialized = false;
+    int64_t steps = 0, corr_samples = 0, series_samples = 0;
+    hipStream_t capture_stream = nullptr;
+    std::map<std::pair<int64_t, const double*>, hipGraphExec_t> graphs;
+    std::string err;
+
+    State st() const
+    {
+        State s;
+        s.r0 = state + lay.r0;
+        s.r1 = lay.r1 ? state + lay.r1 : nullptr;
+        s.a0 = state + lay.a0;
+        s.a1 = lay.a1 ? state + lay.a1 : nullptr;
+        if (res.cfg.precision == SSP_FP64) {
+            s.r1 = nullptr;
+            s.a1 = nullptr;
+        }
+        s.s = reinterpret_cast<int32_t*>(state + lay.s);
+        return s;
+    }
+    ChainTables ct() const
+    {
+        ChainTables c;
+        c.off = reinterpret_cast<const int64_t*>(work + lay.off);
+        c.n = reinterpret_cast<const int32_t*>(work + lay.n);
+        c.elem = reinterpret_cast<const int32_t*>(work + lay.elem);
+        c.gid = reinterpret_cast<const uint32_t*>(work + lay.gid);
+        return c;
+    }
+    int64_t* ctrl() const { return reinterpret_cast<int64_t*>(work + lay.ctrl); }
+    uint32_t* flags() const { return reinterpret_cast<uint32_t*>(work + lay.flags); }
+    double* samples() const { return reinterpret_cast<double*>(work + lay.samples); }
+    Physics phys() const
+    {
+        Physics p;
+        p.dt = res.cfg.dt;
+        p.n0 = res.cfg.n0;
+        p.ns = res.cfg.ns;
+        p.zeta_s = res.cfg.zeta_s;
+        p.key0 = (uint32_t)(res.cfg.seed & 0xffffffffu);
+        p.key1 = (uint32_t)(res.cfg.seed >> 32);
+        return p;
+    }
+};
+
+namespace {
+
+int fail(ssp_handle* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                                                   \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) return fail((h), SSP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s)
+{
+    const ssp_config& k = h->res.cfg;
+    const int64_t M = k.n_chains;
+    for (int64_t done = 0; done < n;) {
+        const int32_t m = (int32_t)std::min<int64_t>(h->lay.chunk, n - done);
+        for (auto& g : h->groups) {
+            StepArgs a{};
+            a.st = h->st();
+            a.ct = h->ct();
+            a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
+            a.n_tasks = g.second.second;
+            a.kappa = kappa;
+            a.thr = reinterpret_cast<const uint32_t*>(h->work + h->lay.thr);
+            a.thr_destroy = threshold(std::min(k.dt / k.zeta_s * 1.0, 1.0));
+            a.ph = h->phys();
+            a.ctrl = h->ctrl();
+            a.n_steps = m;
+            a.sample_every = k.sample_every;
+            a.samples = h->samples();
+            a.n_chains = M;
+            a.flags = h->flags();
+            HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
+        }
+        if (k.corr_levels > 0) {
+            CorrArgs c{};
+            c.samples = h->samples();
+            c.hist = reinterpret_cast<double*>(h->work + h->lay.hist);
+            c.acc = reinterpret_cast<double*>(h->work + h->lay.acc);
+            c.pend = reinterpret_cast<double*>(h->work + h->lay.pend);
+            c.n_chains = M;
+            c.levels = k.corr_levels;
+            c.n_steps = m;
+            c.sample_every = k.sample_every;
+            c.ctrl = h->ctrl();
+            HIPCHK(h, launch_corr(c, s));
+        }
+        if (k.series_capacity > 0) {
+            HIPCHK(h, launch_series(h->samples(), reinterpret_cast<const int32_t*>(h->work + h->lay.elem_off),
+                                    k.n_elements, M, m, k.sample_every, h->lay.q_cap, h->ctrl(),
+                                    reinterpret_cast<double*>(h->work + h->lay.series), k.series_capacity, s));
+        }
+        HIPCHK(h, launch_advance(h->ctrl(), m, k.sample_every, k.series_capacity, h->flags(), s));
+        done += m;
+    }
+    return SSP_OK;
+}
+
+int64_t samples_between(int64_t g0, int64_t n, int32_t every) { return (g0 + n) / every - g0 / every; }
+
+int check_flags(ssp_handle* h, hipStream_t s)
+{
+    uint32_t f = 0;
+    HIPCHK(h, hipMemcpyAsync(&f, h->flags(), sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (f & kFlagNonFinite) return fail(h, SSP_ENONFINITE, "a non-finite bead position was produced");
+    if (f & kFlagInternal) return fail(h, SSP_EHIP, "internal error: slip-spring force gather did not complete");
+    return SSP_OK;
+}
+
+int zero_observables(ssp_handle* h, hipStream_t s)
+{
+    const ssp_config& k = h->res.cfg;
+    const int64_t M = k.n_chains;
+    if (k.corr_levels > 0) {
+        HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.hist), (int64_t)k.corr_levels * 3 * M * 16, s));
+        HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.acc), (int64_t)k.corr_levels * 3 * M * 16, s));
+        HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.pend), 3 * M * 16 * 2, s));
+    }
+    if (k.series_capacity > 0)
+        HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.series),
+                              (int64_t)k.n_elements * k.series_capacity * 6, s));
+    HIPCHK(h, launch_zero_ctrl_obs(h->ctrl(), s));
+    h->corr_samples = 0;
+    h->series_samples = 0;
+    return SSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssp_config_init(ssp_config* c)
+{
+    if (!c) return SSP_EINVAL;
+    std::memset(c, 0, sizeof(*c));
+    c->n_chains = 1;
+    c->n_elements = 1;
+    c->precision = SSP_FP32;
+    c->n_beads = 8;
+    c->sample_every = 1;
+    c->dt = 0.01;
+    c->n0 = 4.0;
+    c->ns = 0.5;
+    c->zeta_s = 0.1;
+    c->seed = 1;
+    c->corr_levels = 16;
+    c->corr_lags = 16;
+    c->corr_batches = 16;
+    c->series_capacity = 0;
+    c->use_graph = 1;
+    return SSP_OK;
+}
+
+int ssp_query_sizes(const ssp_config* cfg, size_t* state_bytes, size_t* work_bytes)
+{
+    Resolved r;
+    if (!resolve(cfg, r, g_create_error)) return SSP_EINVAL;
+    if (cfg->corr_levels > 0 && cfg->corr_batches > cfg->n_chains) {
+        g_create_error = "corr_batches exceeds n_chains";
+        return SSP_EINVAL;
+    }
+    const Layout L = make_layout(r);
+    if (state_bytes) *state_bytes = L.state_total;
+    if (work_bytes) *work_bytes = L.total;
+    return SSP_OK;
+}
+
+int ssp_create(const ssp_config* cfg, void* state_dev, void* work_dev, ssp_handle** out)
+{
+    if (!out) {
+        g_create_error = "null output handle";
+        return SSP_EINVAL;
+    }
+    *out = nullptr;
+    if (!state_dev || !work_dev) {
+        g_create_error = "state and work buffers are required";
+        return SSP_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(state_dev) % kAlign) || (reinterpret_cast<uintptr_t>(work_dev) % kAlign)) {
+        g_create_error = "state and work buffers must be 256-byte aligned";
+        return SSP_EINVAL;
+    }
+    ssp_handle* h = new (std::nothrow) ssp_handle();
+    if (!h) {
+        g_create_error = "out of host memory";
+        return SSP_EINVAL;
+    }
+    if (!resolve(cfg, h->res, g_create_error)) {
+        delete h;
+        return SSP_EINVAL;
+    }
+    h->res.cfg.n_beads_host = nullptr;
+    h->res.cfg.element_offsets_host = nullptr;
+    h->res.cfg.chain_ids_host = nullptr;
+    h->lay = make_layout(h->res);
+    h->state = static_cast<char*>(state_dev);
+    h->work = static_cast<char*>(work_dev);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        g_create_error = "hipGetDevice failed";
+        delete h;
+        return SSP_EHIP;
+    }
+    const int64_t M = h->res.cfg.n_chains;
+    // host tables
+    std::vector<int64_t> off(M);
+    std::vector<int32_t> elem(M);
+    std::vector<uint32_t> gid(M);
+    int64_t o = 0;
+    for (int64_t i = 0; i < M; ++i) {
+        off[i] = o;
+        o += h->res.N[i];
+        gid[i] = (uint32_t)h->res.ids[i];
+    }
+    for (int e = 0; e < h->res.cfg.n_elements; ++e)
+        for (int64_t i = h->res.elem_off[e]; i < h->res.elem_off[e + 1]; ++i) elem[i] = e;
+    // group chains by mapping, keeping chain order inside a group
+    std::map<Mapping, std::vector<int32_t>> by;
+    for (int64_t i = 0; i < M; ++i) by[default_mapping(h->res.N[i])].push_back((int32_t)i);
+    std::vector<int32_t> tasks;
+    tasks.reserve(M);
+    for (auto& kv : by) {
+        h->groups.push_back({kv.first, {(int64_t)tasks.size(), (int64_t)kv.second.size()}});
+        tasks.insert(tasks.end(), kv.second.begin(), kv.second.end());
+    }
+    std::vector<uint32_t> thr(2 * (kMaxBeads + 1), 0u);
+    const ssp_config& k = h->res.cfg;
+    for (int K = 1; K <= kMaxBeads; ++K) {
+        double p = k.dt / (k.zeta_s * k.n0 * (double)K);
+        if (p > 0.5) p = 0.5;
+        thr[K] = threshold(p);
+        thr[kMaxBeads + 1 + K] = threshold(2.0 * p);
+    }
+    auto up = [&](size_t at, const void* src, size_t bytes) {
+        return hipMemcpy(h->work + at, src, bytes, hipMemcpyHostToDevice);
+    };
+    if (up(h->lay.off, off.data(), sizeof(int64_t) * M) != hipSuccess ||
+        up(h->lay.n, h->res.N.data(), sizeof(int32_t) * M) != hipSuccess ||
+        up(h->lay.elem, elem.data(), sizeof(int32_t) * M) != hipSuccess ||
+        up(h->lay.gid, gid.data(), sizeof(uint32_t) * M) != hipSuccess ||
+        up(h->lay.tasks, tasks.data(), sizeof(int32_t) * M) != hipSuccess ||
+        up(h->lay.elem_off, h->res.elem_off.data(), sizeof(int32_t) * h->res.elem_off.size()) != hipSuccess ||
+        up(h->lay.thr, thr.data(), sizeof(uint32_t) * thr.size()) != hipSuccess) {
+        g_create_error = "copying the chain tables to the device failed";
+        delete h;
+        return SSP_EHIP;
+    }
+    if (hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        g_create_error = "hipStreamCreateWithFlags failed";
+        delete h;
+        return SSP_EHIP;
+    }
+    *out = h;
+    return SSP_OK;
+}
+
+int ssp_init_equilibrium(ssp_handle* h, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, launch_reset_ctrl(h->ctrl(), h->flags(), s));
+    HIPCHK(h, launch_init(h->res.cfg.precision, h->st(), h->ct(), h->res.cfg.n_chains, h->phys(), s));
+    int rc = zero_observables(h, s);
+    if (rc) return rc;
+    h->steps = 0;
+    h->initialized = true;
+    return SSP_OK;
+}
+
+int ssp_step(ssp_handle* h, int64_t n_steps, const double* kappa_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!h->initialized) return fail(h, SSP_ESTATE, "ssp_step before ssp_init_equilibrium");
+    if (n_steps < 0) return fail(h, SSP_EINVAL, "n_steps must be >= 0");
+    if (!kappa_dev) return fail(h, SSP_EINVAL, "kappa_dev is required");
+    if (n_steps == 0) return SSP_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    if (h->res.cfg.use_graph) {
+        const auto key = std::make_pair(n_steps, kappa_dev);
+        auto it = h->graphs.find(key);
+        if (it == h->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            HIPCHK(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
+            int rc = enqueue_steps(h, n_steps, kappa_dev, h->capture_stream);
+            hipError_t ec = hipStreamEndCapture(h->capture_stream, &graph);
+            if (rc) return rc;
+            if (ec != hipSuccess) return fail(h, SSP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+            hipGraphExec_t exec = nullptr;
+            ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ec != hipSuccess) return fail(h, SSP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+            it = h->graphs.emplace(key, exec).first;
+        }
+        HIPCHK(h, hipGraphLaunch(it->second, s));
+    } else {
+        int rc = enqueue_steps(h, n_steps, kappa_dev, s);
+        if (rc) return rc;
+    }
+    const int64_t q = samples_between(h->steps, n_steps, h->res.cfg.sample_every);
+    h->steps += n_steps;
+    h->corr_samples += q;
+    h->series_samples += q;
+    return SSP_OK;
+}
+
+int ssp_read_stress(ssp_handle* h, double* out_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!h->initialized) return fail(h, SSP_ESTATE, "read before ssp_init_equilibrium");
+    if (!out_dev) return fail(h, SSP_EINVAL, "out_dev is required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, launch_stress(h->res.cfg.precision, h->st(), h->ct(), h->res.cfg.n_chains, h->res.cfg.ns, out_dev, s));
+    return check_flags(h, s);
+}
+
+int ssp_read_state(ssp_handle* h, double* R_dev, double* A_dev, int32_t* S_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!R_dev || !A_dev || !S_dev) return fail(h, SSP_EINVAL, "R_dev, A_dev and S_dev are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, launch_read_state(h->res.cfg.precision, h->st(), h->res.total_beads, R_dev, A_dev, S_dev, s));
+    return check_flags(h, s);
+}
+
+int ssp_write_state(ssp_handle* h, const double* R_dev, const double* A_dev, const int32_t* S_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!R_dev || !A_dev || !S_dev) return fail(h, SSP_EINVAL, "R_dev, A_dev and S_dev are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    // validate S on the host: it must name a bead of its own chain or be -1
+    std::vector<int32_t> S(h->res.total_beads);
+    HIPCHK(h, hipMemcpyAsync(S.data(), S_dev, sizeof(int32_t) * S.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    int64_t o = 0;
+    for (int64_t c = 0; c < h->res.cfg.n_chains; ++c) {
+        const int n = h->res.N[c];
+        for (int j = 0; j < n; ++j)
+            if (S[o + j] < -1 || S[o + j] >= n) return fail(h, SSP_EINVAL, "S out of range in chain " + std::to_string(c));
+        o += n;
+    }
+    if (!h->initialized) {
+        HIPCHK(h, launch_reset_ctrl(h->ctrl(), h->flags(), s));
+        int rc = zero_observables(h, s);
+        if (rc) return rc;
+        h->steps = 0;
+    }
+    HIPCHK(h, launch_write_state(h->res.cfg.precision, h->st(), h->res.total_beads, R_dev, A_dev, S_dev, s));
+    h->initialized = true;
+    return SSP_OK;
+}
+
+int ssp_read_element_series(ssp_handle* h, double* out_dev, int64_t* n_samples_host, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    const ssp_config& k = h->res.cfg;
+    if (k.series_capacity == 0) return fail(h, SSP_ESTATE, "element series disabled (series_capacity = 0)");
+    if (!out_dev) return fail(h, SSP_EINVAL, "out_dev is required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, hipMemcpyAsync(out_dev, h->work + h->lay.series, sizeof(double) * k.n_elements * k.series_capacity * 6,
+                             hipMemcpyDeviceToDevice, s));
+    if (n_samples_host) *n_samples_host = std::min(h->series_samples, k.series_capacity);
+    return check_flags(h, s);
+}
+
+int ssp_read_correlator(ssp_handle* h, double* G_dev, double* G_err_dev, double* tau_host, int64_t* counts_host,
+                        ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    const ssp_config& k = h->res.cfg;
+    if (k.corr_levels == 0) return fail(h, SSP_ESTATE, "correlator disabled (corr_levels = 0)");
+    if (!G_dev || !G_err_dev) return fail(h, SSP_EINVAL, "G_dev and G_err_dev are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    double* batch = reinterpret_cast<double*>(h->work + h->lay.batch);
+    HIPCHK(h, launch_corr_batches(reinterpret_cast<const double*>(h->work + h->lay.acc), k.n_chains, k.corr_levels,
+                                  k.corr_batches, batch, s));
+    HIPCHK(h, launch_corr_final(batch, k.n_chains, k.corr_levels, k.corr_batches, h->corr_samples, G_dev, G_err_dev, s));
+    for (int l = 0; l < k.corr_levels; ++l)
+        for (int q = 0; q < 16; ++q) {
+            const int64_t len = h->corr_samples >> l;
+            if (tau_host) tau_host[l * 16 + q] = (double)q * std::ldexp(1.0, l) * k.sample_every * k.dt;
+            if (counts_host) counts_host[l * 16 + q] = len > q ? len - q : 0;
+        }
+    return check_flags(h, s);
+}
+
+int ssp_reset_observables(ssp_handle* h, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    return zero_observables(h, s);
+}
+
+int ssp_step_count(const ssp_handle* h, int64_t* steps_host)
+{
+    if (!h || !steps_host) return SSP_EINVAL;
+    *steps_host = h->steps;
+    return SSP_OK;
+}
+
+int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead, int32_t count, double* out_dev,
+                    ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!out_dev || count < 0 || bead < 0 || bead + (int64_t)count > 65536 || chain_id < 0 ||
+        chain_id > (int64_t)UINT32_MAX || step < 0)
+        return fail(h, SSP_EINVAL, "invalid ssp_rng_normals arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    const Physics p = h->phys();
+    HIPCHK(h, launch_rng_normals(h->res.cfg.precision, p.key0, p.key1, (uint32_t)chain_id, step, bead, count, out_dev, s));
+    return SSP_OK;
+}
+
+int ssp_destroy(ssp_handle* h)
+{
+    if (!h) return SSP_OK;
+    (void)hipSetDevice(h->device);
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    delete h;
+    return SSP_OK;
+}
+
+const char* ssp_last_error(const ssp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

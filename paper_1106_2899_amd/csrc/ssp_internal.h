@@ -1,0 +1,111 @@
+// Library-internal declarations shared by the host API and the kernels of
+// libssp.  Not part of the public ABI (include/ssp.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssp {
+
+constexpr int kWaveSize = 64;
+constexpr int kWavesPerGroup = 4;
+constexpr int kGroupThreads = kWaveSize * kWavesPerGroup;
+constexpr int kMaxBeads = 128;
+constexpr int kSampleValues = 12;  // sigma (6) then sigma^v (6)
+constexpr int kCorrLags = 16;
+constexpr int kMaxCorrLevels = 16;
+
+// ctrl[] words in the work buffer (device-resident so that captured graphs
+// can be replayed at any step count).
+enum CtrlWord { kCtrlSteps = 0, kCtrlCorrSamples = 1, kCtrlSeriesSamples = 2, kCtrlWords = 8 };
+enum FlagBits { kFlagNonFinite = 1u, kFlagSeriesOverflow = 2u, kFlagInternal = 4u };
+
+// Random-stream purposes (first counter word = index | purpose << 16).
+enum Purpose : uint32_t {
+    kInitBond = 1,
+    kInitZ = 2,
+    kInitS = 3,
+    kInitAnchor = 4,
+    kNoise = 5,
+    kSlot = 6,
+    kAnchor = 7
+};
+
+struct ChainTables {
+    const int64_t* off;   // [M] first bead / slot entry of the chain
+    const int32_t* n;     // [M] beads (= slots)
+    const int32_t* elem;  // [M] element of the chain
+    const uint32_t* gid;  // [M] global chain id (random-stream key)
+};
+
+// Canonical device state.  FP32: r0 = R hi, r1 = R lo, a0 = A hi, a1 = A lo
+// (float4, w unused).  FP64: r0 = R, a0 = A (double4, w unused); r1, a1 null.
+struct State {
+    void* r0;
+    void* r1;
+    void* a0;
+    void* a1;
+    int32_t* s;
+};
+
+struct Physics {
+    double dt, n0, ns, zeta_s;
+    uint32_t key0, key1;
+};
+
+struct StepArgs {
+    State st;
+    ChainTables ct;
+    const int32_t* tasks;  // chains handled by this launch, one per segment
+    int64_t n_tasks;
+    const double* kappa;   // [E][9]
+    const uint32_t* thr;   // [2][kMaxBeads+1]: integer thresholds for p_K and 2 p_K
+    uint32_t thr_destroy;
+    Physics ph;
+    const int64_t* ctrl;
+    int32_t n_steps;
+    int32_t sample_every;  // 0: no sampling
+    double* samples;       // [Qcap][M][12] or null
+    int64_t n_chains;
+    uint32_t* flags;
+};
+
+struct CorrArgs {
+    const double* samples;  // [Qcap][M][12]
+    double* hist;           // [L][3M][16] lag history of y at each level
+    double* acc;            // [L][3M][16] accumulated x(t) y(t - k)
+    double* pend;           // [3M][16][2] pending (x, y) of level = lane
+    int64_t n_chains;
+    int32_t levels;
+    int32_t n_steps;
+    int32_t sample_every;
+    const int64_t* ctrl;
+};
+
+// Launchers (ssp_kernels.hip).
+hipError_t launch_step(int precision, int W, int B, const StepArgs& a, hipStream_t s);
+hipError_t launch_init(int precision, const State& st, const ChainTables& ct, int64_t M, Physics ph,
+                       hipStream_t s);
+hipError_t launch_reset_ctrl(int64_t* ctrl, uint32_t* flags, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
+hipError_t launch_zero_ctrl_obs(int64_t* ctrl, hipStream_t s);
+hipError_t launch_advance(int64_t* ctrl, int32_t n_steps, int32_t sample_every, int64_t series_cap,
+                          uint32_t* flags, hipStream_t s);
+hipError_t launch_corr(const CorrArgs& a, hipStream_t s);
+hipError_t launch_corr_batches(const double* acc, int64_t n_chains, int32_t levels, int32_t batches,
+                               double* out, hipStream_t s);
+hipError_t launch_corr_final(const double* batch_sums, int64_t n_chains, int32_t levels, int32_t batches,
+                             int64_t corr_samples, double* G, double* G_err, hipStream_t s);
+hipError_t launch_series(const double* samples, const int32_t* elem_off, int32_t n_elements, int64_t n_chains,
+                         int32_t n_steps, int32_t sample_every, int64_t q_cap, const int64_t* ctrl,
+                         double* series, int64_t series_cap, hipStream_t s);
+hipError_t launch_stress(int precision, const State& st, const ChainTables& ct, int64_t M, double ns, double* out,
+                         hipStream_t s);
+hipError_t launch_read_state(int precision, const State& st, int64_t total, double* R, double* A, int32_t* S,
+                             hipStream_t s);
+hipError_t launch_write_state(int precision, const State& st, int64_t total, const double* R, const double* A,
+                              const int32_t* S, hipStream_t s);
+hipError_t launch_rng_normals(int precision, uint32_t key0, uint32_t key1, uint32_t gid, int64_t step, int32_t bead,
+                              int32_t count, double* out, hipStream_t s);
+
+}  // namespace ssp

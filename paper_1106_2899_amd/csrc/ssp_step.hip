@@ -1,0 +1,456 @@
+// The slip-spring ensemble step (three-substep scheme of Sec. 3.1 with the
+// K = C - Z reconstruction of Sec. 3.2), one persistent launch for n steps.
+//
+// Mapping: a wavefront holds 64 / W chains; chain c of the wave owns the
+// lane segment [W c, W c + W).  Lane li of a segment owns beads and slots
+// li*B .. li*B + B - 1 (slot capacity C = N, one slot per bead).  The whole
+// chain state stays in VGPRs for the n steps; it is read from HBM once at
+// launch start and written once at the end.
+//
+// Per step, in the paper's order:
+//   1. forces at time t: bond forces from neighbour exchange, slip-spring
+//      forces gathered per bead (deterministic order of slot index),
+//   2. Euler-Maruyama move of beads and affine advection of anchors,
+//   3. hops decided from the post-move positions (one uniform per spring),
+//   4. destruction at the ends and K = C - Z construction attempts (integer
+//      thresholds, identical in every precision),
+//   5. stress / virtual stress of the new state every sample_every steps,
+//      reduced in FP64 across the segment.
+#include <type_traits>
+
+#include "ssp_device.h"
+#include "ssp_internal.h"
+
+namespace ssp {
+
+namespace {
+
+template <typename T> struct Vec4 {
+    using type = float4;
+};
+template <> struct Vec4<double> {
+    using type = double4;
+};
+
+template <typename T> __device__ __forceinline__ v3<T> ld3(const void* base, int64_t idx)
+{
+    const typename Vec4<T>::type v = reinterpret_cast<const typename Vec4<T>::type*>(base)[idx];
+    return {v.x, v.y, v.z};
+}
+template <typename T> __device__ __forceinline__ void st3(void* base, int64_t idx, v3<T> v)
+{
+    typename Vec4<T>::type o;
+    o.x = v.x;
+    o.y = v.y;
+    o.z = v.z;
+    o.w = T(0);
+    reinterpret_cast<typename Vec4<T>::type*>(base)[idx] = o;
+}
+
+// Value of per-lane array element `elem` held by lane `src` (B elements per lane).
+template <int B, typename T> __device__ __forceinline__ v3<T> gather(const v3<T> (&v)[B], int src, int elem)
+{
+    v3<T> out = lane_read3(v[0], src);
+    if constexpr (B == 2) {
+        const v3<T> o1 = lane_read3(v[1], src);
+        out = elem ? o1 : out;
+    }
+    return out;
+}
+
+__device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ uint32_t lds_load(uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void lds_min(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_fetch_min(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
+
+// Ballot bits of the W-lane segment starting at lane sb.
+template <int W> __device__ __forceinline__ uint64_t seg_mask(int sb)
+{
+    if constexpr (W == 64)
+        return ~0ull;
+    else
+        return ((1ull << W) - 1ull) << sb;
+}
+
+template <typename T> __device__ __forceinline__ bool finite3(v3<T> v)
+{
+    return isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
+}
+
+template <typename T, int W, int B>
+__global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
+{
+    constexpr bool kComp = std::is_same<T, float>::value;  // (hi, lo) position sums
+    constexpr int kChainsPerWave = kWaveSize / W;
+    constexpr int kCap = W * B;  // bead capacity of a segment
+
+    __shared__ uint32_t lds_first[kWavesPerGroup][kWaveSize * B];
+
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wv = threadIdx.x / kWaveSize;
+    const int li = lane % W;
+    const int sb = lane - li;        // first lane of the segment
+    const int seg = lane / W;
+    const int64_t task = ((int64_t)blockIdx.x * kWavesPerGroup + wv) * kChainsPerWave + seg;
+    const bool valid = task < a.n_tasks;
+    const int chain = valid ? a.tasks[task] : 0;
+    const int n = valid ? a.ct.n[chain] : 0;
+    const int64_t off = valid ? a.ct.off[chain] : 0;
+    const uint32_t gid = valid ? a.ct.gid[chain] : 0u;
+    const int elem = valid ? a.ct.elem[chain] : 0;
+    uint32_t* lfirst = lds_first[wv];
+    const int lbase = seg * kCap;  // this segment's first entry in lfirst
+
+    const T dt = T(a.ph.dt);
+    const T ks = T(3.0 / a.ph.ns);                   // slip-spring stiffness 3/N_s
+    const T sq2dt = T(sqrt(2.0 * a.ph.dt));
+    const T ch = T(a.ph.dt / a.ph.zeta_s);           // dt / zeta_s
+    const T qh = T(3.0 / (4.0 * a.ph.ns));           // 3/(4 N_s), Glauber argument scale
+    const T asd = T(sqrt(a.ph.ns / 3.0));            // anchor offset s.d.
+    const uint32_t k0 = a.ph.key0, k1 = a.ph.key1;
+
+    T kap[9];
+    bool has_flow = false;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
+        has_flow |= kap[q] != T(0);
+    }
+    const bool flow = wave_any(has_flow);
+
+    v3<T> rh[B], rl[B], ah[B], al[B], d[B], br[B], bl[B];
+    int s[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = li * B + b;
+        const bool act = i < n;
+        rh[b] = act ? ld3<T>(a.st.r0, off + i) : zero3<T>();
+        ah[b] = act ? ld3<T>(a.st.a0, off + i) : zero3<T>();
+        if constexpr (kComp) {
+            rl[b] = act ? ld3<T>(a.st.r1, off + i) : zero3<T>();
+            al[b] = act ? ld3<T>(a.st.a1, off + i) : zero3<T>();
+        } else {
+            rl[b] = zero3<T>();
+            al[b] = zero3<T>();
+        }
+        s[b] = act ? a.st.s[off + i] : -1;
+    }
+
+    // Bond to the right neighbour (br) and from the left neighbour (bl) of
+    // every bead owned by the lane; zero past the chain ends.
+    auto bonds = [&]() {
+        v3<T> nh = lane_read3(rh[0], lane + 1 < kWaveSize ? lane + 1 : lane);
+        v3<T> nl = lane_read3(rl[0], lane + 1 < kWaveSize ? lane + 1 : lane);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            const v3<T> h = (b + 1 < B) ? rh[b + 1 < B ? b + 1 : b] : nh;
+            const v3<T> l = (b + 1 < B) ? rl[b + 1 < B ? b + 1 : b] : nl;
+            br[b] = (i < n - 1) ? ((h - rh[b]) + (l - rl[b])) : zero3<T>();
+        }
+        const v3<T> left = lane_read3(br[B - 1], lane > 0 ? lane - 1 : lane);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            const v3<T> v = (b > 0) ? br[b > 0 ? b - 1 : 0] : left;
+            bl[b] = (i > 0 && i < n) ? v : zero3<T>();
+        }
+    };
+
+    // Anchor offsets d_j = R_{S_j} - A_j of the occupied slots.
+    {
+        bonds();
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int t = s[b] > 0 ? s[b] : 0;
+            const v3<T> Rh = gather<B>(rh, sb + t / B, t % B);
+            const v3<T> Rl = gather<B>(rl, sb + t / B, t % B);
+            d[b] = (s[b] >= 0) ? ((Rh - ah[b]) + (Rl - al[b])) : zero3<T>();
+        }
+    }
+
+    const int64_t g0 = a.ctrl[kCtrlSteps];
+    bool finite_ok = true;
+
+    for (int step = 0; step < a.n_steps; ++step) {
+        const int64_t g = g0 + step;
+
+        // ---- substep 1a: slip-spring force, sum of d_j over the springs of each
+        // bead, delivered in increasing slot order (one spring per bead per round).
+        v3<T> acc[B];
+        bool pend[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            acc[b] = zero3<T>();
+            pend[b] = s[b] >= 0;
+        }
+        bool any_pend = false;
+#pragma unroll
+        for (int b = 0; b < B; ++b) any_pend |= pend[b];
+        // Every round delivers at least one spring per bead that still has one,
+        // so kCap rounds always suffice; the cap only guards against a hang.
+        for (int round = 0; round <= kCap && wave_any(any_pend); ++round) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) lds_store(&lfirst[lbase + li * B + b], 0xFFFFFFFFu);
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (pend[b]) lds_min(&lfirst[lbase + s[b]], (uint32_t)(lbase + li * B + b));
+            uint32_t got[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) got[b] = lds_load(&lfirst[lbase + li * B + b]);
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (pend[b] && lds_load(&lfirst[lbase + s[b]]) == (uint32_t)(lbase + li * B + b)) pend[b] = false;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const bool have = got[b] != 0xFFFFFFFFu;
+                const int p = have ? (int)got[b] : lbase;
+                const v3<T> v = gather<B>(d, seg * W + (p - lbase) / B, (p - lbase) % B);
+                if (have) acc[b] = acc[b] + v;
+            }
+            any_pend = false;
+#pragma unroll
+            for (int b = 0; b < B; ++b) any_pend |= pend[b];
+        }
+        if (any_pend) atomicOr(a.flags, kFlagInternal);
+
+        // ---- substep 1b: Euler-Maruyama for beads, advection for anchors.
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            const uint4 w = draw(kNoise, (uint32_t)i, gid, g, k0, k1);
+            const v3<T> gn = normals3<T>(w);
+            const v3<T> F = T(3) * (br[b] - bl[b]) - ks * acc[b];
+            const v3<T> r = rh[b];
+            const v3<T> fl = {kap[0] * r.x + kap[1] * r.y + kap[2] * r.z, kap[3] * r.x + kap[4] * r.y + kap[5] * r.z,
+                              kap[6] * r.x + kap[7] * r.y + kap[8] * r.z};
+            const v3<T> inc = dt * (F + fl) + sq2dt * gn;
+            if (i < n) {
+                if constexpr (kComp)
+                    cadd3(rh[b], rl[b], inc);
+                else
+                    rh[b] = rh[b] + inc;
+            }
+        }
+        if (flow) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const v3<T> A = ah[b];
+                const v3<T> inc = dt * v3<T>{kap[0] * A.x + kap[1] * A.y + kap[2] * A.z,
+                                             kap[3] * A.x + kap[4] * A.y + kap[5] * A.z,
+                                             kap[6] * A.x + kap[7] * A.y + kap[8] * A.z};
+                if (s[b] >= 0) {
+                    if constexpr (kComp)
+                        cadd3(ah[b], al[b], inc);
+                    else
+                        ah[b] = ah[b] + inc;
+                }
+            }
+        }
+        bonds();
+
+        // ---- substep 2: hops from the post-move positions.
+        uint4 ws[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = li * B + b;
+            ws[b] = draw(kSlot, (uint32_t)j, gid, g, k0, k1);
+            const int t = s[b] > 0 ? s[b] : 0;
+            const int src = sb + t / B, el = t % B;
+            const v3<T> Rh = gather<B>(rh, src, el);
+            const v3<T> Rl = gather<B>(rl, src, el);
+            const v3<T> bp = gather<B>(br, src, el);   // R_{S+1} - R_S
+            const v3<T> bm = -gather<B>(bl, src, el);  // R_{S-1} - R_S
+            const v3<T> dd = (Rh - ah[b]) + (Rl - al[b]);
+            // (R_{S+-1} - A)^2 - (R_S - A)^2 = b (b + 2 d) with b = R_{S+-1} - R_S
+            const T up = dot(bp, bp + T(2) * dd);
+            const T dn = dot(bm, bm + T(2) * dd);
+            const T pp = (t < n - 1) ? fmin(ch * one_minus_tanh(qh * up), T(0.5)) : T(0);
+            const T pm = (t > 0) ? fmin(ch * one_minus_tanh(qh * dn), T(0.5)) : T(0);
+            const T u = u01<T>(ws[b].x);
+            if (s[b] >= 0) {
+                if (u < pp) {
+                    s[b] = t + 1;
+                    d[b] = dd + bp;
+                } else if (u < pp + pm) {
+                    s[b] = t - 1;
+                    d[b] = dd + bm;
+                } else {
+                    d[b] = dd;
+                }
+            }
+        }
+
+        // ---- substep 3: destruction at the ends, K = C - Z construction attempts.
+        int z = 0;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const uint64_t m = __ballot(s[b] >= 0);
+            const uint64_t segmask = seg_mask<W>(sb);
+            z += __popcll(m & segmask);
+        }
+        const int K = n - z;
+        const uint32_t t1 = a.thr[K < 0 ? 0 : K];
+        const uint32_t t2 = a.thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
+        int create_at[B];
+        bool any_create = false;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = li * B + b;
+            const uint32_t uw = ws[b].y >> 9;
+            create_at[b] = -1;
+            if (j < n) {
+                if (s[b] >= 0) {
+                    if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) {
+                        s[b] = -1;
+                        d[b] = zero3<T>();
+                    }
+                } else if (uw < t1) {
+                    create_at[b] = 0;
+                } else if (uw < t2) {
+                    create_at[b] = n - 1;
+                }
+            }
+            any_create |= create_at[b] >= 0;
+        }
+        if (wave_any(any_create)) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int j = li * B + b;
+                const int at = create_at[b] >= 0 ? create_at[b] : 0;
+                const v3<T> Rh = gather<B>(rh, sb + at / B, at % B);
+                const v3<T> Rl = gather<B>(rl, sb + at / B, at % B);
+                if (create_at[b] >= 0) {
+                    const v3<T> gn = normals3<T>(draw(kAnchor, (uint32_t)j, gid, g, k0, k1));
+                    const v3<T> off3 = asd * gn;
+                    if constexpr (kComp) {
+                        ah[b] = Rh;
+                        al[b] = Rl;
+                        cadd3(ah[b], al[b], off3);
+                        d[b] = (Rh - ah[b]) + (Rl - al[b]);
+                    } else {
+                        ah[b] = Rh + off3;
+                        d[b] = Rh - ah[b];
+                    }
+                    s[b] = create_at[b];
+                }
+            }
+        }
+
+        // ---- observables of the new state.
+        if (a.sample_every > 0 && ((g + 1) % a.sample_every) == 0) {
+            double p[kSampleValues];
+#pragma unroll
+            for (int q = 0; q < kSampleValues; ++q) p[q] = 0.0;
+            const double kss = 3.0 / a.ph.ns;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const double bx = br[b].x, by = br[b].y, bz = br[b].z;  // zero past the end
+                p[0] += 3.0 * bx * bx;
+                p[1] += 3.0 * by * by;
+                p[2] += 3.0 * bz * bz;
+                p[3] += 3.0 * bx * by;
+                p[4] += 3.0 * by * bz;
+                p[5] += 3.0 * bz * bx;
+                const double dx = d[b].x, dy = d[b].y, dz = d[b].z;  // zero when empty
+                p[6] += kss * dx * dx;
+                p[7] += kss * dy * dy;
+                p[8] += kss * dz * dz;
+                p[9] += kss * dx * dy;
+                p[10] += kss * dy * dz;
+                p[11] += kss * dz * dx;
+            }
+#pragma unroll
+            for (int o = W / 2; o >= 1; o >>= 1) {
+#pragma unroll
+                for (int q = 0; q < kSampleValues; ++q) p[q] += __shfl_xor(p[q], o, kWaveSize);
+            }
+            int z2 = 0;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const uint64_t m = __ballot(s[b] >= 0);
+                const uint64_t segmask = seg_mask<W>(sb);
+                z2 += __popcll(m & segmask);
+            }
+            if (valid && li == 0) {
+                const int64_t q = (g + 1) / a.sample_every - g0 / a.sample_every - 1;
+                double* out = a.samples + (q * a.n_chains + chain) * kSampleValues;
+                out[0] = p[0] - n;
+                out[1] = p[1] - n;
+                out[2] = p[2] - n;
+                out[3] = p[3];
+                out[4] = p[4];
+                out[5] = p[5];
+                out[6] = p[6] - z2;
+                out[7] = p[7] - z2;
+                out[8] = p[8] - z2;
+                out[9] = p[9];
+                out[10] = p[10];
+                out[11] = p[11];
+            }
+        }
+    }
+
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = li * B + b;
+        if (i < n) {
+            finite_ok &= finite3(rh[b]);
+            st3<T>(a.st.r0, off + i, rh[b]);
+            st3<T>(a.st.a0, off + i, ah[b]);
+            if constexpr (kComp) {
+                st3<T>(a.st.r1, off + i, rl[b]);
+                st3<T>(a.st.a1, off + i, al[b]);
+            }
+            a.st.s[off + i] = s[b];
+        }
+    }
+    if (!finite_ok) atomicOr(a.flags, kFlagNonFinite);
+}
+
+template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipStream_t s)
+{
+    constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
+    const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
+    if (groups == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_step<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t launch_p(int W, int B, const StepArgs& a, hipStream_t s)
+{
+    if (B == 1) {
+        switch (W) {
+        case 8: return launch_t<T, 8, 1>(a, s);
+        case 16: return launch_t<T, 16, 1>(a, s);
+        case 32: return launch_t<T, 32, 1>(a, s);
+        case 64: return launch_t<T, 64, 1>(a, s);
+        }
+    } else if (B == 2) {
+        switch (W) {
+        case 16: return launch_t<T, 16, 2>(a, s);
+        case 32: return launch_t<T, 32, 2>(a, s);
+        case 64: return launch_t<T, 64, 2>(a, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_step(int precision, int W, int B, const StepArgs& a, hipStream_t s)
+{
+    return precision == 0 ? launch_p<float>(W, B, a, s) : launch_p<double>(W, B, a, s);
+}
+
+}  // namespace ssp

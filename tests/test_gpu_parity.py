@@ -1,0 +1,142 @@
+"""GPU path (libssp through its C ABI) against the FP64 oracle.
+
+The two run the same seeded inputs independently; no value computed on the
+GPU is fed to the oracle.  Compared quantities are translation-invariant:
+bond vectors R_{i+1} - R_i, anchor offsets d_j = R_{S_j} - A_j, slot
+occupancy and bead indices S_j (exact), and stresses.
+
+Tolerances (per step, over 1000 steps):
+  FP64 path: |gpu - oracle| <= 1e-12 * max(|oracle|, 0.58)   (0.58 = rms bond)
+  FP32 path: |gpu - oracle| <= 1e-5  * max(|oracle|, 0.58)
+Decisions (hops, creations, destructions) must agree exactly on the FP64 path.
+On the FP32 path a hop decision may differ only when the oracle's margin
+|u - P| is below 1e-5 (a tie: the FP32 probability carries ~1e-7 relative
+error); such a chain is counted and dropped from later comparison.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+SCALE = 0.58
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+TIE = 1e-5
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _ens(N, M=None, **kw):
+    _need_gpu()
+    from paper_1106_2899_amd.ensemble import Ensemble
+    return Ensemble(N, M, **kw)
+
+
+def _uniform_invariants(R, A, S, M, N):
+    R = R.reshape(M, N, 3)
+    A = A.reshape(M, N, 3)
+    S = S.reshape(M, N)
+    b = R[:, 1:] - R[:, :-1]
+    idx = np.where(S >= 0, S, 0)
+    Rs = np.take_along_axis(R, idx[:, :, None].repeat(3, axis=2), axis=1)
+    d = np.where((S >= 0)[:, :, None], Rs - A, 0.0)
+    return b, d, S
+
+
+def _rel_err(g, o):
+    return np.abs(g - o) / np.maximum(np.abs(o), SCALE)
+
+
+# ----------------------------------------------------------------- RNG -----
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rng_normals_match_oracle(precision):
+    e = _ens(8, 4, precision=precision, seed=12345)
+    got = e.rng_normals(chain_id=77, step=(1 << 33) + 5, bead=3, count=4096).cpu().numpy()
+    want = np.array([oracle.normals3(12345, oracle.P_NOISE, 3 + i, 77, (1 << 33) + 5) for i in range(4096)])
+    err = np.abs(got - want)
+    if precision == "fp64":
+        assert err.max() < 1e-13
+    else:
+        # hardware log2/sin/cos on binary32: absolute error of the normals
+        print("fp32 normals max abs err", err.max(), "rms", math.sqrt((err ** 2).mean()))
+        assert err.max() < 2e-5
+        assert math.sqrt((err ** 2).mean()) < 1e-6
+
+
+# ---------------------------------------------------------------- init -----
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_init_matches_oracle(precision):
+    N = [2, 3, 8, 9, 16, 17, 31, 32, 33, 64, 65, 100, 128]
+    e = _ens(N, precision=precision, seed=7, corr_levels=0).init()
+    o = oracle.Ensemble(N, seed=7).init()
+    R, A, S = (x.cpu().numpy() for x in e.state())
+    assert np.array_equal(S, o.S)
+    np.testing.assert_allclose(R, o.R, rtol=0, atol=1e-13)
+    occ = o.S >= 0
+    np.testing.assert_allclose(A[occ], o.A[occ], rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------- step-by-step parity ---
+
+def _stepwise(precision, M, N, steps, kappa=None, seed=3):
+    e = _ens(N, M, precision=precision, seed=seed, corr_levels=0).init()
+    o = oracle.Ensemble([N] * M, seed=seed).init()
+    kap = None if kappa is None else np.asarray(kappa)
+    alive = np.ones(M, dtype=bool)
+    ties = 0
+    worst = 0.0
+    for t in range(steps):
+        e.step(1, kap)
+        ev, margin = o.step(kap, want_events=True)
+        R, A, S = (x.cpu().numpy() for x in e.state())
+        bg, dg, Sg = _uniform_invariants(R, A, S, M, N)
+        bo, do, So = _uniform_invariants(o.R, o.A, o.S, M, N)
+        mism = (Sg != So) & alive[:, None]
+        if mism.any():
+            rows, cols = np.nonzero(mism)
+            m = margin.reshape(M, N)[rows, cols]
+            assert precision == "fp32", f"decision mismatch on the FP64 path at step {t}: chains {rows}"
+            assert np.all(m < TIE), f"decision mismatch outside a tie at step {t}: margins {m}"
+            ties += len(np.unique(rows))
+            alive[rows] = False
+        a = alive
+        eb = _rel_err(bg[a], bo[a]).max() if a.any() else 0.0
+        occ = (So >= 0) & a[:, None]
+        ed = _rel_err(dg[occ], do[occ]).max() if occ.any() else 0.0
+        worst = max(worst, eb, ed)
+        assert eb <= TOL[precision] and ed <= TOL[precision], (t, eb, ed)
+    return worst, ties, alive.sum()
+
+
+def test_stepwise_parity_fp64_equilibrium_64x8():
+    worst, ties, alive = _stepwise("fp64", 64, 8, 1000)
+    print("fp64 64x8 worst rel err", worst)
+    assert ties == 0
+
+
+def test_stepwise_parity_fp64_shear_32x32():
+    worst, ties, _ = _stepwise("fp64", 32, 32, 400, kappa=[[0, 0.5, 0], [0, 0, 0], [0, 0, 0]])
+    print("fp64 32x32 shear worst rel err", worst)
+    assert ties == 0
+
+
+def test_stepwise_parity_fp32_256x32():
+    worst, ties, alive = _stepwise("fp32", 256, 32, 1000)
+    print("fp32 256x32 worst rel err", worst, "ties", ties)
+    assert alive >= 250
+
+
+def test_stepwise_parity_fp32_shear_128x16():
+    worst, ties, alive = _stepwise("fp32", 128, 16, 500, kappa=[[0, 0.3, 0], [0, 0, 0], [0, 0, 0]], seed=9)
+    print("fp32 128x16 shear worst rel err", worst, "ties", ties)
+    assert alive >= 120
