@@ -1,0 +1,195 @@
+"""Benchmark of the slip-spring ensemble step on one MI355X.
+
+Workload: the equilibrium linear-viscoelasticity ensemble, 16384 chains of
+N = 32 beads (N_0 = 4, N_s = 0.5, zeta_s = 0.1, dt = 0.01), FP32 bead dynamics
+with FP64 stress, stress sampled every 10 steps into the FP64 multiple-tau
+correlator (16 levels x 16 lags).  One benchmark step is one ssp_step call of
+1000 time steps over the whole ensemble (every row of the hot path: RNG,
+forces, Euler move, hops, reconstruction, stress, correlator), replayed from a
+captured hipGraph.  Inputs are resident in HBM before the timed region.
+
+Printed: one JSON line with bead-steps/s of the batched FP32 path, the plain
+FP64 path at the same shape, the VALU roofline of the step kernel (measured
+with HIP events on the launch stream) and the FP64 CPU oracle timed on the
+host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CHAINS, BEADS, SAMPLE_EVERY = 16384, 32, 10
+MD_STEPS_PER_BENCH_STEP = 1000
+PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: full-rate VALU lane-issue slots/s
+
+
+def algorithmic_valu_slots(sample_every: int = SAMPLE_EVERY, n0: float = 4.0) -> float:
+    """VALU issue slots per bead-step that the method needs, weighting each
+    operation by its issue cost on CDNA (full rate = 1; 32x32->64 integer
+    multiply and FP32 transcendentals = 4, quarter rate; FP64 FMA = 1):
+      two Philox4x32-10 blocks (bead noise, slot uniforms): 10 rounds x
+        (2 products x 4 + 2 three-input xors) = 100 each        -> 200
+      Box-Muller, 3 normals: 4 uniforms x 3, 2 log, 2 sqrt,
+        3 sin/cos (x4 each), 5 multiplies                        ->  45
+      forces, flow, Euler move: bonds 3, bond force 6, spring 3,
+        kappa.R 9, increment 9, position update 3                ->  33
+      hop per occupied slot (fraction 1/N_0): offset 3, two energy
+        differences 12, two probabilities 2 x 12, decision 3     ->  42 / N_0
+      reconstruction threshold tests                             ->   2
+      stress and virtual stress products (FP64), per sample      -> 7.5 / n_s
+    """
+    return 200.0 + 45.0 + 33.0 + 42.0 / n0 + 2.0 + 7.5 / sample_every
+
+
+def _sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _traffic_from_profiles(kernel_src):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "step_kernel_lve_16384x32_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            d = json.load(f)
+        if d.get("kernel_source_sha256") != _sha(kernel_src):
+            return None
+        return float(d["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def run_gpu(precision, md_steps, steps, warmup, timing=False, use_graph=True):
+    import torch
+
+    from paper_1106_2899_amd.ensemble import Ensemble
+
+    e = Ensemble(BEADS, CHAINS, precision=precision, seed=2, sample_every=SAMPLE_EVERY, corr_levels=16,
+                 corr_batches=16, max_steps_per_launch=md_steps, use_graph=use_graph)
+    e.init()
+    e.step(md_steps)  # first call captures the graph
+    torch.cuda.synchronize()
+    if timing:
+        e.set_kernel_timing(True)
+    for _ in range(warmup):
+        e.step(md_steps)
+    torch.cuda.synchronize()
+    if timing:
+        e.kernel_time()  # discard warm-up launches
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e.step(md_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = e.kernel_time() if timing else None
+    stress = e.stress()  # raises if a non-finite state was produced
+    assert torch.isfinite(stress).all()
+    e.close()
+    return t1 - t0, kt
+
+
+def cpu_baseline(sample_chains=512, sample_steps=4000):
+    import oracle
+
+    oracle.build(force=False)
+    o = oracle.Ensemble([BEADS] * sample_chains, seed=2).init()
+    t0 = time.perf_counter()
+    o.run(sample_steps, sample_every=SAMPLE_EVERY, keep_samples=False)
+    dt = time.perf_counter() - t0
+    return {
+        "value": sample_chains * BEADS * sample_steps / dt,
+        "unit": "bead-steps/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"{sample_chains} chains x N={BEADS} x {sample_steps} steps of the same workload "
+                  f"(sampling every {SAMPLE_EVERY} steps), FP64, OpenMP over chains; {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    md = MD_STEPS_PER_BENCH_STEP
+    beads = CHAINS * BEADS
+    # batched FP32 (headline), graph replay
+    t32, _ = run_gpu("fp32", md, args.steps, args.warmup)
+    v32 = beads * md * args.steps / t32
+    # plain FP64 at the same shape (fewer steps: same per-step work, slower path)
+    k64 = max(2, args.steps // 4)
+    t64, _ = run_gpu("fp64", md, k64, 1)
+    v64 = beads * md * k64 / t64
+    # roofline leg: step-kernel launch durations from HIP events on the launch stream
+    _, (ms, launches, bead_steps) = run_gpu("fp32", md, max(3, args.steps // 4), 1, timing=True, use_graph=False)
+    per_launch_s = ms / 1e3 / launches
+    slots = algorithmic_valu_slots()
+    achieved = slots * (bead_steps / launches) / per_launch_s
+    kernel_src = os.path.join(ROOT, "paper_1106_2899_amd", "csrc", "ssp_step.hip")
+    roofline = {
+        "bound": "alu",
+        "kernel": "k_step<float,32,1>",
+        "achieved": achieved,
+        "peak": PEAK_LANE_SLOTS,
+        "unit": "VALU lane-slots/s",
+        "frac": achieved / PEAK_LANE_SLOTS,
+        "traffic": _traffic_from_profiles(kernel_src),
+        "algorithmic_slots_per_bead_step": slots,
+        "launch_ms": per_launch_s * 1e3,
+        "bead_steps_per_launch": bead_steps / launches,
+    }
+    out = {
+        "metric": "bead-steps/sec on 1 MI355X (batched FP32 vs plain FP64); adjoint/forward time ratio",
+        "value": v32,
+        "unit": "bead-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "lve_16384x32",
+            "chains": CHAINS,
+            "beads": BEADS,
+            "time_steps_per_bench_step": md,
+            "sample_every": SAMPLE_EVERY,
+            "correlator": "multiple-tau 16x16 FP64",
+            "n0": 4.0, "ns": 0.5, "zeta_s": 0.1, "dt": 0.01,
+        },
+        "fp64_plain": {"value": v64, "unit": "bead-steps/s", "steps": k64, "ms_per_step": t64 / k64 * 1e3},
+        "fp32_over_fp64": v32 / v64,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

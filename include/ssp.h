@@ -128,9 +128,7 @@ int ssp_read_stress(ssp_handle* h, double* out_dev, ssp_stream stream);
 
 /* Canonical FP64 view of the state: R_dev [sum N][3], A_dev [sum N][3]
  * (hi + lo for the FP32 path), S_dev [sum N] int32 (bead index 0..N-1, or
- * -1 for an empty slot).  Positions may have been shifted by a common
- * per-chain vector (re-centring); every physical quantity depends only on
- * R_i - R_i' and R_{S_j} - A_j, which the shift leaves unchanged.
+ * -1 for an empty slot; the anchor of an empty slot is meaningless).
  * Synchronises the stream. */
 int ssp_read_state(ssp_handle* h, double* R_dev, double* A_dev, int32_t* S_dev, ssp_stream stream);
 
@@ -172,6 +170,16 @@ int ssp_step_count(const ssp_handle* h, int64_t* steps_host);
  * Used to test the random streams in isolation. */
 int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead, int32_t count, double* out_dev,
                     ssp_stream stream);
+
+/* Kernel timing mode (for measurement): while enabled, ssp_step launches
+ * without a graph and brackets the step-kernel launches of every chunk with
+ * hipEvents on the caller's stream. */
+int ssp_set_kernel_timing(ssp_handle* h, int enable);
+
+/* Synchronises the recorded events and returns the summed step-kernel time in
+ * ms, the number of timed chunks and the bead-steps they covered since the
+ * previous call; then clears the totals. */
+int ssp_kernel_time(ssp_handle* h, double* ms_host, int64_t* launches_host, int64_t* bead_steps_host);
 
 /* Releases host resources (graphs, capture stream).  Caller memory untouched. */
 int ssp_destroy(ssp_handle* h);

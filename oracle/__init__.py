@@ -64,6 +64,8 @@ def lib():
                                      ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, f64p, f64p, i32p, f64p]
         L.ssp_oracle_run.restype = ctypes.c_int64
         L.ssp_oracle_multitau.argtypes = [ctypes.c_int64, f64p, f64p, ctypes.c_int, ctypes.c_int, f64p, i64p]
+        L.ssp_oracle_threads.argtypes = []
+        L.ssp_oracle_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -79,6 +81,11 @@ def philox(counter, key):
     out = np.zeros(4, dtype=np.uint32)
     lib().ssp_oracle_philox(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(out, ctypes.c_uint32))
     return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops over chains use."""
+    return int(lib().ssp_oracle_threads())
 
 
 def u01(w: int) -> float:

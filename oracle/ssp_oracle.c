@@ -45,9 +45,13 @@
  * (w0,w1) and the cosine member of the pair from (w2,w3).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads the OpenMP loops over chains use. */
+int ssp_oracle_threads(void) { return omp_get_max_threads(); }
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846

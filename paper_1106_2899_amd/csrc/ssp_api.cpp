@@ -229,6 +229,11 @@ struct ssp_handle {
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int64_t, const double*>, hipGraphExec_t> graphs;
     std::string err;
+    // kernel timing mode: events bracket every step-kernel launch
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0, timed_bead_steps = 0;
 
     State st() const
     {
@@ -289,6 +294,12 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s)
     const int64_t M = k.n_chains;
     for (int64_t done = 0; done < n;) {
         const int32_t m = (int32_t)std::min<int64_t>(h->lay.chunk, n - done);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->timing) {
+            HIPCHK(h, hipEventCreate(&e0));
+            HIPCHK(h, hipEventCreate(&e1));
+            HIPCHK(h, hipEventRecord(e0, s));
+        }
         for (auto& g : h->groups) {
             StepArgs a{};
             a.st = h->st();
@@ -306,6 +317,11 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s)
             a.n_chains = M;
             a.flags = h->flags();
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
+        }
+        if (h->timing) {
+            HIPCHK(h, hipEventRecord(e1, s));
+            h->events.push_back({e0, e1});
+            h->timed_bead_steps += h->res.total_beads * (int64_t)m;
         }
         if (k.corr_levels > 0) {
             CorrArgs c{};
@@ -512,7 +528,7 @@ int ssp_step(ssp_handle* h, int64_t n_steps, const double* kappa_dev, ssp_stream
     if (n_steps == 0) return SSP_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIPCHK(h, hipSetDevice(h->device));
-    if (h->res.cfg.use_graph) {
+    if (h->res.cfg.use_graph && !h->timing) {
         const auto key = std::make_pair(n_steps, kappa_dev);
         auto it = h->graphs.find(key);
         if (it == h->graphs.end()) {
@@ -654,10 +670,44 @@ int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead,
     return SSP_OK;
 }
 
+int ssp_set_kernel_timing(ssp_handle* h, int enable)
+{
+    if (!h) return SSP_EINVAL;
+    h->timing = enable != 0;
+    return SSP_OK;
+}
+
+int ssp_kernel_time(ssp_handle* h, double* ms_host, int64_t* launches_host, int64_t* bead_steps_host)
+{
+    if (!h) return SSP_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    for (auto& ev : h->events) {
+        HIPCHK(h, hipEventSynchronize(ev.second));
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, ev.first, ev.second));
+        h->timed_ms += ms;
+        ++h->timed_launches;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    h->events.clear();
+    if (ms_host) *ms_host = h->timed_ms;
+    if (launches_host) *launches_host = h->timed_launches;
+    if (bead_steps_host) *bead_steps_host = h->timed_bead_steps;
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+    h->timed_bead_steps = 0;
+    return SSP_OK;
+}
+
 int ssp_destroy(ssp_handle* h)
 {
     if (!h) return SSP_OK;
     (void)hipSetDevice(h->device);
+    for (auto& ev : h->events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     delete h;

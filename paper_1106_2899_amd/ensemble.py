@@ -219,6 +219,16 @@ class Ensemble:
         self.stream.synchronize()
         return out
 
+    def set_kernel_timing(self, enable: bool) -> "Ensemble":
+        self._chk(lib().ssp_set_kernel_timing(self._h, 1 if enable else 0))
+        return self
+
+    def kernel_time(self):
+        """(ms, launches, bead_steps) of the step kernels timed since the last call."""
+        ms, n, bs = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._chk(lib().ssp_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(bs)))
+        return ms.value, n.value, bs.value
+
     # ------------------------------------------------------- derived views
     def bonds_and_offsets(self):
         """Translation-invariant view: bonds [sumN,3] (R_{i+1}-R_i, NaN at each

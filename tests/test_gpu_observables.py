@@ -1,0 +1,157 @@
+"""GPU observables and launch configurations against the FP64 oracle.
+
+Covers: the multiple-tau correlator (G(t) in the Green-Kubo form with the
+virtual stress), per-element stress series (viscosity growth), the stress
+read-out, every chain-to-wavefront mapping (W = 8, 16, 32, 64 lanes per
+chain; two beads per lane for N > 64) with mixed shear/elongation elements,
+bitwise invariance to graph replay and launch chunking, and the non-finite
+latch.  The oracle runs the same seeded inputs on its own.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _ens(N, M=None, **kw):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1106_2899_amd.ensemble import Ensemble
+    return Ensemble(N, M, **kw)
+
+
+def _oracle_G(samples, levels):
+    """G[l][k] = sum over chains and xy, yz, zx of C / (3 M cnt)."""
+    T, M, _ = samples.shape
+    tot = np.zeros((levels, 16))
+    cnt = None
+    for k in range(M):
+        for c in range(3):
+            x = samples[:, k, 3 + c]
+            y = x + samples[:, k, 9 + c]
+            C, n = oracle.multitau(x, y, levels=levels, lags=16)
+            tot += C
+            cnt = n
+    with np.errstate(invalid="ignore", divide="ignore"):
+        G = np.where(cnt > 0, tot / (3.0 * M * np.maximum(cnt, 1)), 0.0)
+    return G, cnt
+
+
+def test_chunking_and_graph_invariance_bitwise():
+    kw = dict(precision="fp32", seed=4, sample_every=3, corr_levels=6, corr_batches=4)
+    kap = [[0, 0.2, 0], [0, 0, 0], [0, 0, 0]]
+    a = _ens(20, 64, use_graph=True, **kw).init()
+    b = _ens(20, 64, use_graph=False, max_steps_per_launch=7, **kw).init()
+    a.step(300, kap)
+    for _ in range(6):
+        b.step(50, kap)
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)
+    ca, cb = a.correlator(), b.correlator()
+    assert np.array_equal(ca["G"], cb["G"]) and np.array_equal(ca["counts"], cb["counts"])
+    # replaying the cached graph continues the same trajectory
+    a.step(300, kap)
+    for _ in range(6):
+        b.step(50, kap)
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)
+
+
+def test_correlator_matches_oracle_fp64():
+    M, N, every, steps, L = 32, 8, 3, 3000, 10
+    e = _ens(N, M, precision="fp64", seed=6, sample_every=every, corr_levels=L, corr_batches=4).init()
+    e.step(steps)
+    got = e.correlator()
+    o = oracle.Ensemble([N] * M, seed=6).init()
+    s = o.run(steps, sample_every=every)
+    G, cnt = _oracle_G(s, L)
+    assert np.array_equal(got["counts"], cnt)
+    np.testing.assert_allclose(got["G"], G, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(got["tau"][0], np.arange(16) * every * 0.01)
+    assert np.all(got["G_err"][cnt > 0] >= 0)
+
+
+def test_correlator_matches_oracle_fp32_statistically_close():
+    M, N, every, steps, L = 64, 16, 2, 2000, 8
+    e = _ens(N, M, precision="fp32", seed=8, sample_every=every, corr_levels=L, corr_batches=8).init()
+    e.step(steps)
+    got = e.correlator()
+    o = oracle.Ensemble([N] * M, seed=8).init()
+    G, cnt = _oracle_G(o.run(steps, sample_every=every), L)
+    # same trajectories up to FP32 rounding (1e-5 relative per step) and rare ties
+    ok = cnt > 0
+    np.testing.assert_allclose(got["G"][ok], G[ok], rtol=1e-3, atol=1e-3 * np.abs(G[ok]).max())
+
+
+def test_element_series_matches_oracle_fp64():
+    E, per, N, steps, every = 4, 16, 12, 500, 5
+    rates = [0.0, 0.05, 0.5, 2.0]
+    kap = np.zeros((E, 3, 3))
+    kap[:, 0, 1] = rates
+    e = _ens(N, E * per, n_elements=E, precision="fp64", seed=10, sample_every=every, corr_levels=0,
+             series_capacity=200).init()
+    e.step(steps, kap)
+    ser = e.element_series().cpu().numpy()
+    assert ser.shape == (E, steps // every, 6)
+    o = oracle.Ensemble([N] * (E * per), seed=10).init()
+    s = o.run(steps, kappa=np.repeat(kap.reshape(E, 9), per, axis=0), sample_every=every)
+    want = s[:, :, :6].reshape(steps // every, E, per, 6).sum(axis=2).transpose(1, 0, 2)
+    np.testing.assert_allclose(ser, want, rtol=1e-10, atol=1e-9)
+
+
+def test_stress_readout_matches_oracle_fp64():
+    M, N = 40, 24
+    e = _ens(N, M, precision="fp64", seed=12, corr_levels=0).init()
+    e.step(200)
+    o = oracle.Ensemble([N] * M, seed=12).init()
+    o.run(200, keep_samples=False)
+    np.testing.assert_allclose(e.stress().cpu().numpy(), o.stress(), rtol=1e-11, atol=1e-10)
+
+
+LENGTHS = [2, 5, 8, 9, 15, 16, 17, 24, 32, 33, 48, 64, 65, 90, 127, 128]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_mapping_mixed_flows(precision):
+    N = LENGTHS * 4
+    M = len(N)
+    offs = [0, M // 2, M]
+    kap = np.stack([np.array([[0, 0.3, 0], [0, 0, 0], [0, 0, 0]]), np.diag([0.05, -0.025, -0.025])])
+    e = _ens(N, n_elements=2, element_offsets=offs, precision=precision, seed=14, corr_levels=0).init()
+    o = oracle.Ensemble(N, seed=14).init()
+    kchain = np.repeat(kap.reshape(2, 9), [M // 2, M - M // 2], axis=0)
+    steps = 300
+    e.step(steps, kap)
+    o.run(steps, kappa=kchain, keep_samples=False)
+    R, A, S = (x.cpu().numpy() for x in e.state())
+    from paper_1106_2899_amd.ensemble import _invariants
+    bg, dg, Sg = _invariants(R, A, S, np.array(N), e.offsets)
+    bo, do, So = _invariants(o.R, o.A, o.S, np.array(N), o.off)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    same_chain = np.array([np.array_equal(Sg[e.offsets[k]:e.offsets[k] + N[k]], So[o.off[k]:o.off[k] + N[k]])
+                           for k in range(M)])
+    if precision == "fp64":
+        assert same_chain.all()
+    else:
+        assert same_chain.sum() >= M - 3
+    for k in np.nonzero(same_chain)[0]:
+        sl = slice(e.offsets[k], e.offsets[k] + N[k])
+        b_ok = ~np.isnan(bo[sl][:, 0])
+        err = np.abs(bg[sl][b_ok] - bo[sl][b_ok]) / np.maximum(np.abs(bo[sl][b_ok]), 0.58)
+        assert err.max() <= tol, (k, N[k], err.max())
+        occ = So[sl] >= 0
+        if occ.any():
+            err = np.abs(dg[sl][occ] - do[sl][occ]) / np.maximum(np.abs(do[sl][occ]), 0.58)
+            assert err.max() <= tol, (k, N[k], err.max())
+
+
+def test_nonfinite_state_is_reported():
+    from paper_1106_2899_amd import SspError
+    e = _ens(16, 8, precision="fp32", seed=1, corr_levels=0).init()
+    e.step(2000, np.diag([400.0, -200.0, -200.0]))  # elongation far beyond the Rouse stability limit
+    with pytest.raises(SspError) as ei:
+        e.stress()
+    assert ei.value.code == -4
