@@ -98,7 +98,7 @@ def run_gpu(precision, md_steps, steps, warmup, timing=False, use_graph=True):
     return t1 - t0, kt
 
 
-def cpu_baseline(sample_chains=512, sample_steps=4000):
+def cpu_baseline(sample_chains=4096, sample_steps=16000):
     import oracle
 
     oracle.build(force=False)

@@ -167,9 +167,10 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         }
     };
 
-    // Anchor offsets d_j = R_{S_j} - A_j of the occupied slots.
-    {
-        bonds();
+    // Anchor offsets d_j = R_{S_j} - A_j of the occupied slots, always
+    // recomputed from the stored positions (never carried across a step) so
+    // that a trajectory does not depend on how steps are split into launches.
+    auto refresh_offsets = [&]() {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int t = s[b] > 0 ? s[b] : 0;
@@ -177,7 +178,9 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             const v3<T> Rl = gather<B>(rl, sb + t / B, t % B);
             d[b] = (s[b] >= 0) ? ((Rh - ah[b]) + (Rl - al[b])) : zero3<T>();
         }
-    }
+    };
+    bonds();
+    refresh_offsets();
 
     const int64_t g0 = a.ctrl[kCtrlSteps];
     bool finite_ok = true;
@@ -279,15 +282,10 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             const T pm = (t > 0) ? fmin(ch * one_minus_tanh(qh * dn), T(0.5)) : T(0);
             const T u = u01<T>(ws[b].x);
             if (s[b] >= 0) {
-                if (u < pp) {
+                if (u < pp)
                     s[b] = t + 1;
-                    d[b] = dd + bp;
-                } else if (u < pp + pm) {
+                else if (u < pp + pm)
                     s[b] = t - 1;
-                    d[b] = dd + bm;
-                } else {
-                    d[b] = dd;
-                }
             }
         }
 
@@ -311,10 +309,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             create_at[b] = -1;
             if (j < n) {
                 if (s[b] >= 0) {
-                    if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) {
-                        s[b] = -1;
-                        d[b] = zero3<T>();
-                    }
+                    if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) s[b] = -1;
                 } else if (uw < t1) {
                     create_at[b] = 0;
                 } else if (uw < t2) {
@@ -337,15 +332,14 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
                         ah[b] = Rh;
                         al[b] = Rl;
                         cadd3(ah[b], al[b], off3);
-                        d[b] = (Rh - ah[b]) + (Rl - al[b]);
                     } else {
                         ah[b] = Rh + off3;
-                        d[b] = Rh - ah[b];
                     }
                     s[b] = create_at[b];
                 }
             }
         }
+        refresh_offsets();
 
         // ---- observables of the new state.
         if (a.sample_every > 0 && ((g + 1) % a.sample_every) == 0) {

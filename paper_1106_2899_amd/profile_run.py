@@ -1,0 +1,35 @@
+"""Short, fixed GPU runs for rocprofv3 (kernel trace and counter passes).
+
+    python -m paper_1106_2899_amd.profile_run step   # step kernel, 16384 x N=32, 3 launches of 1000 steps
+    python -m paper_1106_2899_amd.profile_run copy   # 1 GiB read + 1 GiB write elementwise copy (counter calibration)
+"""
+from __future__ import annotations
+
+import sys
+
+import torch
+
+
+def step(launches: int = 3, md_steps: int = 1000) -> None:
+    from .ensemble import Ensemble
+
+    e = Ensemble(32, 16384, precision="fp32", seed=2, sample_every=10, corr_levels=16, corr_batches=16,
+                 max_steps_per_launch=md_steps, use_graph=False)
+    e.init()
+    for _ in range(launches):
+        e.step(md_steps)
+    torch.cuda.synchronize()
+    print("step launches:", launches, "bead-steps per launch:", 16384 * 32 * md_steps, flush=True)
+
+
+def copy(nbytes: int = 1 << 30) -> None:
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 1.0, out=b)  # reads nbytes, writes nbytes
+    torch.cuda.synchronize()
+    print("copy bytes read:", nbytes, "written:", nbytes, flush=True)
+
+
+if __name__ == "__main__":
+    {"step": step, "copy": copy}[sys.argv[1]]()
