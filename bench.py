@@ -56,17 +56,18 @@ def _sha(path):
 def _traffic_from_profiles(kernel_src):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when absent or taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", "step_kernel_lve_16384x32_traffic.json")
+    p = os.path.join(ROOT, "profiles", "step_kernel_lve_16384x32_counters.md")
     if not os.path.exists(p):
         return None
-    try:
-        with open(p) as f:
-            d = json.load(f)
-        if d.get("kernel_source_sha256") != _sha(kernel_src):
-            return None
-        return float(d["hbm_bytes_per_launch"])
-    except Exception:
+    d = {}
+    with open(p) as f:
+        for line in f:
+            k, _, v = line.strip().partition(": ")
+            if k in ("kernel_source_sha256", "hbm_bytes_per_launch"):
+                d[k] = v.strip()
+    if d.get("kernel_source_sha256") != _sha(kernel_src) or "hbm_bytes_per_launch" not in d:
         return None
+    return float(d["hbm_bytes_per_launch"])
 
 
 def run_gpu(precision, md_steps, steps, warmup, timing=False, use_graph=True):
