@@ -66,6 +66,11 @@ def lib():
         L.ssp_oracle_multitau.argtypes = [ctypes.c_int64, f64p, f64p, ctypes.c_int, ctypes.c_int, f64p, i64p]
         L.ssp_oracle_threads.argtypes = []
         L.ssp_oracle_threads.restype = ctypes.c_int
+        L.ssp_oracle_step_forced.argtypes = [ctypes.c_int, i32p, i64p, i64p, f64p, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_uint64, ctypes.c_int64, f64p, f64p, i32p, i32p]
+        L.ssp_oracle_adjoint.argtypes = [ctypes.c_int, i32p, i64p, i64p, f64p, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, f64p, f64p, i32p,
+                                         ctypes.c_int64, ctypes.c_int, ctypes.c_int, f64p, f64p]
         _lib = L
     return _lib
 
@@ -190,6 +195,46 @@ class Ensemble:
                                 _p(self.R, ctypes.c_double), _p(self.A, ctypes.c_double), _p(self.S, ctypes.c_int32),
                                 _p(out, ctypes.c_double))
         return out
+
+    # ---- frozen-event forward and discrete adjoint -------------------------
+    def run_record(self, n_steps, kappa=None):
+        """n_steps steps keeping the full trajectory: R, A [(n+1)][tot][3], S [(n+1)][tot]."""
+        Rt = np.zeros((n_steps + 1, self.total, 3))
+        At = np.zeros((n_steps + 1, self.total, 3))
+        St = np.zeros((n_steps + 1, self.total), dtype=np.int32)
+        Rt[0], At[0], St[0] = self.R, self.A, self.S
+        for t in range(n_steps):
+            self.step(kappa)
+            Rt[t + 1], At[t + 1], St[t + 1] = self.R, self.A, self.S
+        return Rt, At, St
+
+    def step_forced(self, S_next, kappa=None, ns=None):
+        """One step with the slot decisions given (S after the step)."""
+        Np, op, cp = self._ptrs()
+        k = self._kappa(kappa)
+        sn = np.ascontiguousarray(S_next, dtype=np.int32)
+        lib().ssp_oracle_step_forced(self.M, Np, op, cp, _p(k, ctypes.c_double), self.dt,
+                                     self.ns if ns is None else float(ns), self.seed, self.step_index,
+                                     _p(self.R, ctypes.c_double), _p(self.A, ctypes.c_double),
+                                     _p(self.S, ctypes.c_int32), _p(sn, ctypes.c_int32))
+        self.step_index += 1
+
+    def adjoint(self, Rt, At, St, kappa=None, step0=0, comp=3, init_window=True):
+        """dJ/dkappa [M][3][3] and dJ/dN_s [M] of J = sigma_comp at the end of the
+        recorded window (comp: 0..5 = xx yy zz xy yz zx)."""
+        Np, op, cp = self._ptrs()
+        k = self._kappa(kappa)
+        T = Rt.shape[0] - 1
+        Rt = np.ascontiguousarray(Rt, dtype=np.float64)
+        At = np.ascontiguousarray(At, dtype=np.float64)
+        St = np.ascontiguousarray(St, dtype=np.int32)
+        gk = np.zeros((self.M, 9))
+        gns = np.zeros(self.M)
+        lib().ssp_oracle_adjoint(self.M, Np, op, cp, _p(k, ctypes.c_double), self.dt, self.ns, self.seed, step0, T,
+                                 _p(Rt, ctypes.c_double), _p(At, ctypes.c_double), _p(St, ctypes.c_int32),
+                                 self.total, comp, 1 if init_window else 0, _p(gk, ctypes.c_double),
+                                 _p(gns, ctypes.c_double))
+        return gk.reshape(self.M, 3, 3), gns
 
     # Relative, translation-invariant views used for comparisons.
     def bonds(self):

@@ -237,22 +237,17 @@ double ssp_oracle_hop_prob(int n, const double* r, const double* aj, int i, int 
  * sum_b kappa[a][b] R_b.  Optional outputs (may be NULL): events[slot] bits
  * above; margin[slot] = smallest |u - threshold| over the decisions that slot
  * took in this step (1.0 when it took none). */
-static void step_chain(int n, int64_t c, const double* kap, double dt, double n0, double ns, double zeta_s,
-                       uint64_t seed, int64_t step, double* r, double* a, int32_t* s, uint8_t* ev,
-                       double* margin, double* F, double* ro)
+/* Substep 1 of Sec. 3.1 for one chain: forces F = -dJ/dR at time t (free
+ * energy of Sec. 2.1) with the slot state s, then the Euler-Maruyama move of
+ * the beads and the affine advection of the occupied anchors. */
+static void move_chain(int n, int64_t c, const double* kap, double dt, double ns, uint64_t seed, int64_t step,
+                       double* r, double* a, const int32_t* s, double* F, double* ro)
 {
     const double kb = 3.0;
     const double ks = 3.0 / ns;
     const double sq2dt = sqrt(2.0 * dt);
-    const double anchor_sd = sqrt(ns / 3.0);
-    const double ch = dt / zeta_s;
 
-    if (ev)
-        for (int j = 0; j < n; ++j) ev[j] = 0;
-    if (margin)
-        for (int j = 0; j < n; ++j) margin[j] = 1.0;
-
-    /* Substep 1: forces F = -dJ/dR at time t (Eq. for the free energy, Sec. 2.1). */
+    for (int i = 0; i < 3 * n; ++i) F[i] = 0.0;
     for (int i = 0; i < 3 * n; ++i) F[i] = 0.0;
     for (int i = 0; i + 1 < n; ++i) {
         for (int d = 0; d < 3; ++d) {
@@ -284,6 +279,22 @@ static void step_chain(int n, int64_t c, const double* kap, double dt, double n0
             a[3 * j + d] += dt * flow;
         }
     }
+}
+
+static void step_chain(int n, int64_t c, const double* kap, double dt, double n0, double ns, double zeta_s,
+                       uint64_t seed, int64_t step, double* r, double* a, int32_t* s, uint8_t* ev,
+                       double* margin, double* F, double* ro)
+{
+    const double anchor_sd = sqrt(ns / 3.0);
+    const double ch = dt / zeta_s;
+
+    if (ev)
+        for (int j = 0; j < n; ++j) ev[j] = 0;
+    if (margin)
+        for (int j = 0; j < n; ++j) margin[j] = 1.0;
+
+    /* Substep 1: move. */
+    move_chain(n, c, kap, dt, ns, seed, step, r, a, s, F, ro);
 
     /* Substep 2: hops, all springs from the same post-Langevin positions. */
     uint32_t w[4];
@@ -497,4 +508,182 @@ void ssp_oracle_multitau(int64_t T, const double* x, const double* y, int levels
     }
     free(xl);
     free(yl);
+}
+
+/* ---- Frozen-event step and discrete adjoint ------------------------------
+ * The derivative of a finite-time stress with respect to the flow rate or the
+ * slip-spring strength is taken conditioned on the recorded hop, creation and
+ * destruction events and on the random normals (pathwise derivative of the
+ * Euler map of Sec. 3.1 with the events held fixed).  The dependence of the
+ * event probabilities on the parameters is not part of it. */
+
+/* One step whose slot decisions are given: the substep-1 move with the
+ * current slots, then S := S_next; a slot that goes from empty to occupied is
+ * a spring created at bead S_next with anchor R' + sqrt(N_s/3) g (the anchor
+ * normals of that slot and step); a slot that goes from occupied to empty is a
+ * destroyed spring. */
+void ssp_oracle_step_forced(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
+                            const double* kappa, double dt, double ns, uint64_t seed, int64_t step, double* R,
+                            double* A, int32_t* S, const int32_t* S_next)
+{
+    const double anchor_sd = sqrt(ns / 3.0);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int k = 0; k < n_chains; ++k) {
+        int n = N[k];
+        int64_t o = off[k];
+        double* r = R + 3 * o;
+        double* a = A + 3 * o;
+        int32_t* s = S + o;
+        const int32_t* sn = S_next + o;
+        double* F = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        double* ro = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        move_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, ns, seed, step, r, a, s, F, ro);
+        for (int j = 0; j < n; ++j) {
+            if (s[j] < 0 && sn[j] >= 0) {
+                double g[3];
+                ssp_oracle_normals3(seed, P_ANCHOR, j, chain_id[k], step, g);
+                for (int d = 0; d < 3; ++d) a[3 * j + d] = r[3 * sn[j] + d] + anchor_sd * g[d];
+            } else if (sn[j] < 0) {
+                a[3 * j] = a[3 * j + 1] = a[3 * j + 2] = 0.0;
+            }
+            s[j] = sn[j];
+        }
+        free(F);
+        free(ro);
+    }
+}
+
+/* Indices of the stress components: xx yy zz xy yz zx. */
+static const int COMP_A[6] = {0, 1, 2, 0, 1, 2};
+static const int COMP_B[6] = {0, 1, 2, 1, 2, 0};
+
+/* Gradient of J = sigma_comp(R_T) of every chain with respect to the velocity
+ * gradient kappa (9 entries, constant over the window) and to N_s, by the
+ * reverse recursion through steps T-1 .. 0 of the window.
+ *
+ * Rt [(T+1)][tot][3], At [(T+1)][tot][3], St [(T+1)][tot]: the state before
+ * step step0 + n at index n (n = 0..T).  kappa [M][9].  If init_window, the
+ * anchors at index 0 are the sampled equilibrium anchors A = R_S +
+ * sqrt(N_s/3) g(INIT_ANCHOR) and their N_s dependence is included.
+ * Outputs gk [M][9], gns [M].
+ *
+ * Per step n (state x_n = (R_n, A_n), slots S_n -> S_{n+1}):
+ *   R_{n+1} = R_n + dt (F(R_n, A_n; S_n) + kappa R_n) + noise,
+ *   A_{n+1,j} = A_{n,j} + dt kappa A_{n,j}        (slot occupied before and after),
+ *   A_{n+1,j} = R_{n+1,S_{n+1,j}} + sqrt(N_s/3) g  (slot created in step n);
+ * with lR = dJ/dR_{n+1}, lA = dJ/dA_{n+1}:
+ *   lR[e_j] += lA[j] for created slots, dJ/dN_s += lA[j] . g / (2 sqrt(3 N_s));
+ *   dJ/dR_n = lR + dt (L lR - (3/N_s) c lR + kappa^T lR)   (L: bond Laplacian,
+ *             c_i: springs on bead i at step n);
+ *   dJ/dA_n[j] = (1 + dt kappa^T) lA[j] (surviving) + dt (3/N_s) lR[S_{n,j}];
+ *   dJ/dkappa_ab += dt (sum_i lR_ia R_{n,i,b} + sum_surviving j lA_ja A_{n,j,b});
+ *   dJ/dN_s += dt (3/N_s^2) sum_j lR[S_{n,j}] . (R_{n,S_j} - A_{n,j}). */
+void ssp_oracle_adjoint(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
+                        const double* kappa, double dt, double ns, uint64_t seed, int64_t step0, int64_t T,
+                        const double* Rt, const double* At, const int32_t* St, int64_t tot, int comp,
+                        int init_window, double* gk, double* gns)
+{
+    const double ks = 3.0 / ns;
+    const double dsig = 1.0 / (2.0 * sqrt(3.0 * ns));
+    const int ca = COMP_A[comp], cb = COMP_B[comp];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int k = 0; k < n_chains; ++k) {
+        const int n = N[k];
+        const int64_t o = off[k];
+        const double* kap = kappa + 9 * (int64_t)k;
+        double* lR = (double*)calloc(3 * (size_t)n, sizeof(double));
+        double* lA = (double*)calloc(3 * (size_t)n, sizeof(double));
+        double* nR = (double*)calloc(3 * (size_t)n, sizeof(double));
+        double* nA = (double*)calloc(3 * (size_t)n, sizeof(double));
+        int* cnt = (int*)calloc((size_t)n, sizeof(int));
+        double G[9] = {0}, Gns = 0.0;
+        /* seed: dJ/dR_T of sigma_ab = sum_i 3 b_ia b_ib */
+        const double* RT = Rt + 3 * (T * tot + o);
+        for (int i = 0; i + 1 < n; ++i) {
+            double b[3];
+            for (int d = 0; d < 3; ++d) b[d] = RT[3 * (i + 1) + d] - RT[3 * i + d];
+            double g[3] = {0.0, 0.0, 0.0};
+            g[ca] += 3.0 * b[cb];
+            g[cb] += 3.0 * b[ca];
+            for (int d = 0; d < 3; ++d) {
+                lR[3 * (i + 1) + d] += g[d];
+                lR[3 * i + d] -= g[d];
+            }
+        }
+        for (int64_t m = T - 1; m >= 0; --m) {
+            const double* Rn = Rt + 3 * (m * tot + o);
+            const double* An = At + 3 * (m * tot + o);
+            const int32_t* Sn = St + m * tot + o;
+            const int32_t* S1 = St + (m + 1) * tot + o;
+            /* created slots feed their anchor adjoint to the end bead */
+            for (int j = 0; j < n; ++j) {
+                if (Sn[j] < 0 && S1[j] >= 0) {
+                    double g[3];
+                    ssp_oracle_normals3(seed, P_ANCHOR, j, chain_id[k], step0 + m, g);
+                    for (int d = 0; d < 3; ++d) {
+                        lR[3 * S1[j] + d] += lA[3 * j + d];
+                        Gns += lA[3 * j + d] * g[d] * dsig;
+                    }
+                }
+            }
+            for (int i = 0; i < n; ++i) cnt[i] = 0;
+            for (int j = 0; j < n; ++j)
+                if (Sn[j] >= 0) ++cnt[Sn[j]];
+            /* parameter terms of step m (use lR = dJ/dR_{m+1}, lA = dJ/dA_{m+1}) */
+            for (int i = 0; i < n; ++i)
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) G[3 * a + b] += dt * lR[3 * i + a] * Rn[3 * i + b];
+            for (int j = 0; j < n; ++j) {
+                if (Sn[j] >= 0 && S1[j] >= 0)
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) G[3 * a + b] += dt * lA[3 * j + a] * An[3 * j + b];
+                if (Sn[j] >= 0) {
+                    const int i = Sn[j];
+                    for (int d = 0; d < 3; ++d) Gns += dt * (3.0 / (ns * ns)) * lR[3 * i + d] * (Rn[3 * i + d] - An[3 * j + d]);
+                }
+            }
+            /* dJ/dR_m */
+            for (int i = 0; i < n; ++i) {
+                for (int d = 0; d < 3; ++d) {
+                    double lap = 0.0;
+                    if (i + 1 < n) lap += 3.0 * (lR[3 * (i + 1) + d] - lR[3 * i + d]);
+                    if (i > 0) lap -= 3.0 * (lR[3 * i + d] - lR[3 * (i - 1) + d]);
+                    double kt = kap[0 * 3 + d] * lR[3 * i + 0] + kap[1 * 3 + d] * lR[3 * i + 1] + kap[2 * 3 + d] * lR[3 * i + 2];
+                    nR[3 * i + d] = lR[3 * i + d] + dt * (lap - ks * cnt[i] * lR[3 * i + d] + kt);
+                }
+            }
+            /* dJ/dA_m */
+            for (int j = 0; j < n; ++j) {
+                for (int d = 0; d < 3; ++d) nA[3 * j + d] = 0.0;
+                if (Sn[j] < 0) continue;
+                if (S1[j] >= 0) {
+                    for (int d = 0; d < 3; ++d) {
+                        double kt = kap[0 * 3 + d] * lA[3 * j + 0] + kap[1 * 3 + d] * lA[3 * j + 1] + kap[2 * 3 + d] * lA[3 * j + 2];
+                        nA[3 * j + d] = lA[3 * j + d] + dt * kt;
+                    }
+                }
+                for (int d = 0; d < 3; ++d) nA[3 * j + d] += dt * ks * lR[3 * Sn[j] + d];
+            }
+            for (int q = 0; q < 3 * n; ++q) {
+                lR[q] = nR[q];
+                lA[q] = nA[q];
+            }
+        }
+        if (init_window) {
+            const int32_t* S0 = St + o;
+            for (int j = 0; j < n; ++j) {
+                if (S0[j] < 0) continue;
+                double g[3];
+                ssp_oracle_normals3(seed, P_INIT_ANCHOR, j, chain_id[k], 0, g);
+                for (int d = 0; d < 3; ++d) Gns += lA[3 * j + d] * g[d] * dsig;
+            }
+        }
+        for (int q = 0; q < 9; ++q) gk[9 * (int64_t)k + q] = G[q];
+        gns[k] = Gns;
+        free(lR);
+        free(lA);
+        free(nR);
+        free(nA);
+        free(cnt);
+    }
 }
