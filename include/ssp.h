@@ -171,6 +171,16 @@ int ssp_step_count(const ssp_handle* h, int64_t* steps_host);
 int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead, int32_t count, double* out_dev,
                     ssp_stream stream);
 
+/* Chain-to-wavefront mapping for the chains with n_lo <= N <= n_hi: each
+ * such chain occupies lanes_per_chain lanes (8, 16, 32 or 64) with
+ * beads_per_lane beads and slots per lane (1, or 2 with 16, 32 or 64 lanes);
+ * lanes_per_chain * beads_per_lane >= n_hi.  Trajectories do not depend on the
+ * mapping (each bead's arithmetic is the same); FP64 stress sums may differ in
+ * the last bits.  The default is the narrowest one-bead-per-lane segment that
+ * fits (two beads per lane for N > 64).  Synchronises the device; drops
+ * captured graphs.  Used by the autotuner. */
+int ssp_set_mapping(ssp_handle* h, int32_t n_lo, int32_t n_hi, int32_t lanes_per_chain, int32_t beads_per_lane);
+
 /* Kernel timing mode (for measurement): while enabled, ssp_step launches
  * without a graph and brackets the step-kernel launches of every chunk with
  * hipEvents on the caller's stream. */

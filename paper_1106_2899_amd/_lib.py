@@ -35,6 +35,7 @@ EXPORTS = [
     "ssp_reset_observables",
     "ssp_step_count",
     "ssp_rng_normals",
+    "ssp_set_mapping",
     "ssp_set_kernel_timing",
     "ssp_kernel_time",
     "ssp_destroy",
@@ -101,6 +102,7 @@ def lib():
             "ssp_reset_observables": [vp, vp],
             "ssp_step_count": [vp, ctypes.POINTER(ctypes.c_int64)],
             "ssp_rng_normals": [vp, i64, i64, i32, i32, vp, vp],
+            "ssp_set_mapping": [vp, i32, i32, i32, i32],
             "ssp_set_kernel_timing": [vp, ctypes.c_int],
             "ssp_kernel_time": [vp, f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
             "ssp_destroy": [vp],

@@ -41,6 +41,13 @@ Mapping default_mapping(int n)
     return {64, 2};
 }
 
+bool mapping_supported(int W, int B)
+{
+    if (B == 1) return W == 8 || W == 16 || W == 32 || W == 64;
+    if (B == 2) return W == 16 || W == 32 || W == 64;
+    return false;
+}
+
 struct Layout {
     // work buffer offsets (bytes)
     size_t ctrl, flags, off, n, elem, gid, tasks, elem_off, thr, samples, hist, acc, pend, batch, series, corr_out,
@@ -224,6 +231,7 @@ struct ssp_handle {
     char* state = nullptr;
     char* work = nullptr;
     std::vector<std::pair<Mapping, std::pair<int64_t, int64_t>>> groups;  // mapping, [task begin, count)
+    std::vector<Mapping> chain_map;                                       // mapping of every chain
     bool initialized = false;
     int64_t steps = 0, corr_samples = 0, series_samples = 0;
     hipStream_t capture_stream = nullptr;
@@ -349,6 +357,22 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s)
 
 int64_t samples_between(int64_t g0, int64_t n, int32_t every) { return (g0 + n) / every - g0 / every; }
 
+// Groups chains by their mapping (chain order kept inside a group) and
+// returns the concatenated task list; h->groups receives the ranges.
+std::vector<int32_t> group_tasks(ssp_handle* h)
+{
+    std::map<Mapping, std::vector<int32_t>> by;
+    for (size_t i = 0; i < h->chain_map.size(); ++i) by[h->chain_map[i]].push_back((int32_t)i);
+    std::vector<int32_t> tasks;
+    tasks.reserve(h->chain_map.size());
+    h->groups.clear();
+    for (auto& kv : by) {
+        h->groups.push_back({kv.first, {(int64_t)tasks.size(), (int64_t)kv.second.size()}});
+        tasks.insert(tasks.end(), kv.second.begin(), kv.second.end());
+    }
+    return tasks;
+}
+
 int check_flags(ssp_handle* h, hipStream_t s)
 {
     uint32_t f = 0;
@@ -465,15 +489,9 @@ int ssp_create(const ssp_config* cfg, void* state_dev, void* work_dev, ssp_handl
     }
     for (int e = 0; e < h->res.cfg.n_elements; ++e)
         for (int64_t i = h->res.elem_off[e]; i < h->res.elem_off[e + 1]; ++i) elem[i] = e;
-    // group chains by mapping, keeping chain order inside a group
-    std::map<Mapping, std::vector<int32_t>> by;
-    for (int64_t i = 0; i < M; ++i) by[default_mapping(h->res.N[i])].push_back((int32_t)i);
-    std::vector<int32_t> tasks;
-    tasks.reserve(M);
-    for (auto& kv : by) {
-        h->groups.push_back({kv.first, {(int64_t)tasks.size(), (int64_t)kv.second.size()}});
-        tasks.insert(tasks.end(), kv.second.begin(), kv.second.end());
-    }
+    h->chain_map.resize(M);
+    for (int64_t i = 0; i < M; ++i) h->chain_map[i] = default_mapping(h->res.N[i]);
+    const std::vector<int32_t> tasks = group_tasks(h);
     std::vector<uint32_t> thr(2 * (kMaxBeads + 1), 0u);
     const ssp_config& k = h->res.cfg;
     for (int K = 1; K <= kMaxBeads; ++K) {
@@ -667,6 +685,26 @@ int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead,
     HIPCHK(h, hipSetDevice(h->device));
     const Physics p = h->phys();
     HIPCHK(h, launch_rng_normals(h->res.cfg.precision, p.key0, p.key1, (uint32_t)chain_id, step, bead, count, out_dev, s));
+    return SSP_OK;
+}
+
+int ssp_set_mapping(ssp_handle* h, int32_t n_lo, int32_t n_hi, int32_t lanes_per_chain, int32_t beads_per_lane)
+{
+    if (!h) return SSP_EINVAL;
+    if (n_lo < 2 || n_hi < n_lo || n_hi > SSP_MAX_BEADS) return fail(h, SSP_EINVAL, "need 2 <= n_lo <= n_hi <= 128");
+    if (!mapping_supported(lanes_per_chain, beads_per_lane))
+        return fail(h, SSP_EINVAL, "unsupported mapping (lanes 8/16/32/64 with 1 bead per lane, 16/32/64 with 2)");
+    if (lanes_per_chain * beads_per_lane < n_hi)
+        return fail(h, SSP_EINVAL, "lanes_per_chain * beads_per_lane must be >= n_hi");
+    HIPCHK(h, hipSetDevice(h->device));
+    const int64_t M = h->res.cfg.n_chains;
+    for (int64_t i = 0; i < M; ++i)
+        if (h->res.N[i] >= n_lo && h->res.N[i] <= n_hi) h->chain_map[i] = {lanes_per_chain, beads_per_lane};
+    const std::vector<int32_t> tasks = group_tasks(h);
+    HIPCHK(h, hipDeviceSynchronize());  // no launch may still read the old task list
+    HIPCHK(h, hipMemcpy(h->work + h->lay.tasks, tasks.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
     return SSP_OK;
 }
 

@@ -21,7 +21,9 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-        c = make_uint4((uint32_t)(m1 >> 32) ^ c.y ^ k0, (uint32_t)m1, (uint32_t)(m0 >> 32) ^ c.w ^ k1, (uint32_t)m0);
+        // three-input xor in one v_bitop3_b32 (truth table 0x96)
+        c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), c.y, k0, 0x96), (uint32_t)m1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c.w, k1, 0x96), (uint32_t)m0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -65,8 +67,8 @@ __device__ __forceinline__ v3<float> normals3_f32(uint4 w)
 {
     const float u0 = u01<float>(w.x), u1 = u01<float>(w.y), u2 = u01<float>(w.z), u3 = u01<float>(w.w);
     // -2 ln u = -2 ln2 log2 u; the hardware sine/cosine take revolutions.
-    const float r1 = __builtin_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u0));
-    const float r2 = __builtin_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u2));
+    const float r1 = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u0));
+    const float r2 = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u2));
     return {r1 * __builtin_amdgcn_cosf(u1), r1 * __builtin_amdgcn_sinf(u1), r2 * __builtin_amdgcn_cosf(u3)};
 }
 
@@ -93,6 +95,26 @@ __device__ __forceinline__ float one_minus_tanh(float x)
     return 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
 }
 __device__ __forceinline__ double one_minus_tanh(double x) { return 2.0 / (1.0 + exp(2.0 * x)); }
+
+// Neighbour exchange across the whole wavefront with DPP: lane i receives
+// lane i+1 (from_next, wave_shl:1) or lane i-1 (from_prev, wave_shr:1); the
+// lane without a source receives 0.
+__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_next(float v) { return __builtin_bit_cast(float, dpp_next_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float from_prev(float v) { return __builtin_bit_cast(float, dpp_prev_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double from_next(double v)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(dpp_next_i(p.x), dpp_next_i(p.y)));
+}
+__device__ __forceinline__ double from_prev(double v)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(dpp_prev_i(p.x), dpp_prev_i(p.y)));
+}
+template <typename T> __device__ __forceinline__ v3<T> from_next3(v3<T> v) { return {from_next(v.x), from_next(v.y), from_next(v.z)}; }
+template <typename T> __device__ __forceinline__ v3<T> from_prev3(v3<T> v) { return {from_prev(v.x), from_prev(v.y), from_prev(v.z)}; }
 
 // Cross-lane reads (ds_bpermute).
 __device__ __forceinline__ float lane_read(float v, int src) { return __shfl(v, src, kWaveSize); }

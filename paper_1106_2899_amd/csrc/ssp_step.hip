@@ -7,15 +7,25 @@
 // chain state stays in VGPRs for the n steps; it is read from HBM once at
 // launch start and written once at the end.
 //
+// Cross-lane data paths:
+//   - neighbour bonds: DPP wave shifts (VALU, no LDS traffic);
+//   - per-bead records {R hi, R lo, bond right, bond left} are staged in a
+//     wave-private LDS array after the move; slots read the record of their
+//     bead for the hop, for new anchors and for the anchor offsets;
+//   - the slot -> bead force scatter is a deterministic gather: in rounds,
+//     pending springs ds_min their slot index into their bead's LDS word and
+//     each bead adds the winner's offset d (read from LDS) in increasing slot
+//     order; no float atomics, so runs are bitwise reproducible;
+//   - stress sums: FP64 reduce-scatter butterfly over the segment.
+//
 // Per step, in the paper's order:
-//   1. forces at time t: bond forces from neighbour exchange, slip-spring
-//      forces gathered per bead (deterministic order of slot index),
+//   1. forces at time t: bond forces and slip-spring forces,
 //   2. Euler-Maruyama move of beads and affine advection of anchors,
 //   3. hops decided from the post-move positions (one uniform per spring),
 //   4. destruction at the ends and K = C - Z construction attempts (integer
 //      thresholds, identical in every precision),
-//   5. stress / virtual stress of the new state every sample_every steps,
-//      reduced in FP64 across the segment.
+//   5. anchor offsets recomputed from the stored positions, and the stress /
+//      virtual stress of the new state every sample_every steps.
 #include <type_traits>
 
 #include "ssp_device.h"
@@ -47,15 +57,30 @@ template <typename T> __device__ __forceinline__ void st3(void* base, int64_t id
     reinterpret_cast<typename Vec4<T>::type*>(base)[idx] = o;
 }
 
-// Value of per-lane array element `elem` held by lane `src` (B elements per lane).
-template <int B, typename T> __device__ __forceinline__ v3<T> gather(const v3<T> (&v)[B], int src, int elem)
+// Per-bead record staged in LDS: R hi, R lo, bond to the right, bond from the left.
+template <typename T> struct alignas(16) BeadRec {
+    T v[12];
+};
+template <typename T> struct alignas(16) Off4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void rec_put(BeadRec<T>& r, v3<T> rh, v3<T> rl, v3<T> br, v3<T> bl)
 {
-    v3<T> out = lane_read3(v[0], src);
-    if constexpr (B == 2) {
-        const v3<T> o1 = lane_read3(v[1], src);
-        out = elem ? o1 : out;
-    }
-    return out;
+    BeadRec<T> t;
+    t.v[0] = rh.x; t.v[1] = rh.y; t.v[2] = rh.z;
+    t.v[3] = rl.x; t.v[4] = rl.y; t.v[5] = rl.z;
+    t.v[6] = br.x; t.v[7] = br.y; t.v[8] = br.z;
+    t.v[9] = bl.x; t.v[10] = bl.y; t.v[11] = bl.z;
+    r = t;
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v)
@@ -87,6 +112,18 @@ template <typename T> __device__ __forceinline__ bool finite3(v3<T> v)
     return isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
 }
 
+// Wave-private LDS: the bead records double as the transpose buffer of the
+// stress sums ([64 lanes][12] FP64), which is used only after the records of
+// a step have been consumed.
+template <typename T, int B> struct WaveLds {
+    static constexpr int kRecBytes = (int)sizeof(BeadRec<T>) * kWaveSize * B;
+    static constexpr int kSumBytes = (int)sizeof(double) * kWaveSize * kSampleValues;
+    static constexpr int kShared = kRecBytes > kSumBytes ? kRecBytes : kSumBytes;
+    alignas(16) unsigned char shared[kShared];
+    Off4<T> off[kWaveSize * B];
+    uint32_t first[kWaveSize * B];
+};
+
 template <typename T, int W, int B>
 __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 {
@@ -94,13 +131,13 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     constexpr int kChainsPerWave = kWaveSize / W;
     constexpr int kCap = W * B;  // bead capacity of a segment
 
-    __shared__ uint32_t lds_first[kWavesPerGroup][kWaveSize * B];
+    __shared__ WaveLds<T, B> lds[kWavesPerGroup];
 
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wv = threadIdx.x / kWaveSize;
     const int li = lane % W;
-    const int sb = lane - li;        // first lane of the segment
     const int seg = lane / W;
+    const int sb = lane - li;  // first lane of the segment
     const int64_t task = ((int64_t)blockIdx.x * kWavesPerGroup + wv) * kChainsPerWave + seg;
     const bool valid = task < a.n_tasks;
     const int chain = valid ? a.tasks[task] : 0;
@@ -108,8 +145,11 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     const int64_t off = valid ? a.ct.off[chain] : 0;
     const uint32_t gid = valid ? a.ct.gid[chain] : 0u;
     const int elem = valid ? a.ct.elem[chain] : 0;
-    uint32_t* lfirst = lds_first[wv];
-    const int lbase = seg * kCap;  // this segment's first entry in lfirst
+    uint32_t* lfirst = lds[wv].first;
+    BeadRec<T>* rec = reinterpret_cast<BeadRec<T>*>(lds[wv].shared);
+    double* sums = reinterpret_cast<double*>(lds[wv].shared);
+    Off4<T>* offs = lds[wv].off;
+    const int lbase = seg * kCap;  // this segment's first entry in the LDS arrays
 
     const T dt = T(a.ph.dt);
     const T ks = T(3.0 / a.ph.ns);                   // slip-spring stiffness 3/N_s
@@ -146,11 +186,12 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         s[b] = act ? a.st.s[off + i] : -1;
     }
 
-    // Bond to the right neighbour (br) and from the left neighbour (bl) of
-    // every bead owned by the lane; zero past the chain ends.
-    auto bonds = [&]() {
-        v3<T> nh = lane_read3(rh[0], lane + 1 < kWaveSize ? lane + 1 : lane);
-        v3<T> nl = lane_read3(rl[0], lane + 1 < kWaveSize ? lane + 1 : lane);
+    // Bonds to the right neighbour (br) and from the left neighbour (bl) of
+    // every bead owned by the lane (zero past the chain ends), then the bead
+    // records in LDS.
+    auto bonds_and_records = [&]() {
+        const v3<T> nh = from_next3(rh[0]);
+        const v3<T> nl = from_next3(rl[0]);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
@@ -158,28 +199,41 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             const v3<T> l = (b + 1 < B) ? rl[b + 1 < B ? b + 1 : b] : nl;
             br[b] = (i < n - 1) ? ((h - rh[b]) + (l - rl[b])) : zero3<T>();
         }
-        const v3<T> left = lane_read3(br[B - 1], lane > 0 ? lane - 1 : lane);
+        const v3<T> left = from_prev3(br[B - 1]);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
             const v3<T> v = (b > 0) ? br[b > 0 ? b - 1 : 0] : left;
             bl[b] = (i > 0 && i < n) ? v : zero3<T>();
         }
+#pragma unroll
+        for (int b = 0; b < B; ++b) rec_put(rec[lbase + li * B + b], rh[b], rl[b], br[b], bl[b]);
+        wave_sync();
     };
 
     // Anchor offsets d_j = R_{S_j} - A_j of the occupied slots, always
     // recomputed from the stored positions (never carried across a step) so
-    // that a trajectory does not depend on how steps are split into launches.
+    // that a trajectory does not depend on how steps are split into launches;
+    // also staged in LDS for the next force gather.
     auto refresh_offsets = [&]() {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int t = s[b] > 0 ? s[b] : 0;
-            const v3<T> Rh = gather<B>(rh, sb + t / B, t % B);
-            const v3<T> Rl = gather<B>(rl, sb + t / B, t % B);
+            const BeadRec<T> r = rec[lbase + t];
+            const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
+            const v3<T> Rl = {r.v[3], r.v[4], r.v[5]};
             d[b] = (s[b] >= 0) ? ((Rh - ah[b]) + (Rl - al[b])) : zero3<T>();
+            Off4<T> o;
+            o.v[0] = d[b].x;
+            o.v[1] = d[b].y;
+            o.v[2] = d[b].z;
+            o.v[3] = T(0);
+            offs[lbase + li * B + b] = o;
         }
+        wave_sync();
     };
-    bonds();
+
+    bonds_and_records();
     refresh_offsets();
 
     const int64_t g0 = a.ctrl[kCtrlSteps];
@@ -192,14 +246,13 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         // bead, delivered in increasing slot order (one spring per bead per round).
         v3<T> acc[B];
         bool pend[B];
+        bool any_pend = false;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             acc[b] = zero3<T>();
             pend[b] = s[b] >= 0;
+            any_pend |= pend[b];
         }
-        bool any_pend = false;
-#pragma unroll
-        for (int b = 0; b < B; ++b) any_pend |= pend[b];
         // Every round delivers at least one spring per bead that still has one,
         // so kCap rounds always suffice; the cap only guards against a hang.
         for (int round = 0; round <= kCap && wave_any(any_pend); ++round) {
@@ -211,19 +264,19 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             uint32_t got[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) got[b] = lds_load(&lfirst[lbase + li * B + b]);
-#pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (pend[b] && lds_load(&lfirst[lbase + s[b]]) == (uint32_t)(lbase + li * B + b)) pend[b] = false;
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const bool have = got[b] != 0xFFFFFFFFu;
-                const int p = have ? (int)got[b] : lbase;
-                const v3<T> v = gather<B>(d, seg * W + (p - lbase) / B, (p - lbase) % B);
-                if (have) acc[b] = acc[b] + v;
-            }
             any_pend = false;
 #pragma unroll
-            for (int b = 0; b < B; ++b) any_pend |= pend[b];
+            for (int b = 0; b < B; ++b) {
+                if (pend[b] && lds_load(&lfirst[lbase + s[b]]) == (uint32_t)(lbase + li * B + b)) pend[b] = false;
+                any_pend |= pend[b];
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (got[b] != 0xFFFFFFFFu) {
+                    const Off4<T> o = offs[got[b]];
+                    acc[b] = acc[b] + v3<T>{o.v[0], o.v[1], o.v[2]};
+                }
+            }
         }
         if (any_pend) atomicOr(a.flags, kFlagInternal);
 
@@ -260,7 +313,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
                 }
             }
         }
-        bonds();
+        bonds_and_records();
 
         // ---- substep 2: hops from the post-move positions.
         uint4 ws[B];
@@ -269,11 +322,11 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             const int j = li * B + b;
             ws[b] = draw(kSlot, (uint32_t)j, gid, g, k0, k1);
             const int t = s[b] > 0 ? s[b] : 0;
-            const int src = sb + t / B, el = t % B;
-            const v3<T> Rh = gather<B>(rh, src, el);
-            const v3<T> Rl = gather<B>(rl, src, el);
-            const v3<T> bp = gather<B>(br, src, el);   // R_{S+1} - R_S
-            const v3<T> bm = -gather<B>(bl, src, el);  // R_{S-1} - R_S
+            const BeadRec<T> r = rec[lbase + t];
+            const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
+            const v3<T> Rl = {r.v[3], r.v[4], r.v[5]};
+            const v3<T> bp = {r.v[6], r.v[7], r.v[8]};      // R_{S+1} - R_S
+            const v3<T> bm = {-r.v[9], -r.v[10], -r.v[11]};  // R_{S-1} - R_S
             const v3<T> dd = (Rh - ah[b]) + (Rl - al[b]);
             // (R_{S+-1} - A)^2 - (R_S - A)^2 = b (b + 2 d) with b = R_{S+-1} - R_S
             const T up = dot(bp, bp + T(2) * dd);
@@ -292,11 +345,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         // ---- substep 3: destruction at the ends, K = C - Z construction attempts.
         int z = 0;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const uint64_t m = __ballot(s[b] >= 0);
-            const uint64_t segmask = seg_mask<W>(sb);
-            z += __popcll(m & segmask);
-        }
+        for (int b = 0; b < B; ++b) z += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
         const int K = n - z;
         const uint32_t t1 = a.thr[K < 0 ? 0 : K];
         const uint32_t t2 = a.thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
@@ -322,12 +371,11 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int j = li * B + b;
-                const int at = create_at[b] >= 0 ? create_at[b] : 0;
-                const v3<T> Rh = gather<B>(rh, sb + at / B, at % B);
-                const v3<T> Rl = gather<B>(rl, sb + at / B, at % B);
                 if (create_at[b] >= 0) {
-                    const v3<T> gn = normals3<T>(draw(kAnchor, (uint32_t)j, gid, g, k0, k1));
-                    const v3<T> off3 = asd * gn;
+                    const BeadRec<T> r = rec[lbase + create_at[b]];
+                    const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
+                    const v3<T> Rl = {r.v[3], r.v[4], r.v[5]};
+                    const v3<T> off3 = asd * normals3<T>(draw(kAnchor, (uint32_t)j, gid, g, k0, k1));
                     if constexpr (kComp) {
                         ah[b] = Rh;
                         al[b] = Rl;
@@ -364,34 +412,25 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
                 p[10] += kss * dy * dz;
                 p[11] += kss * dz * dx;
             }
-#pragma unroll
-            for (int o = W / 2; o >= 1; o >>= 1) {
-#pragma unroll
-                for (int q = 0; q < kSampleValues; ++q) p[q] += __shfl_xor(p[q], o, kWaveSize);
-            }
             int z2 = 0;
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const uint64_t m = __ballot(s[b] >= 0);
-                const uint64_t segmask = seg_mask<W>(sb);
-                z2 += __popcll(m & segmask);
+            for (int b = 0; b < B; ++b) z2 += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
+            // Transpose through LDS: lane li < 12 of a segment sums value li
+            // over the segment's lanes in lane order (deterministic).
+#pragma unroll
+            for (int q = 0; q < kSampleValues; ++q) sums[lane * kSampleValues + q] = p[q];
+            wave_sync();
+            if (li < kSampleValues) {
+                double tot = 0.0;
+#pragma unroll 8
+                for (int r = 0; r < W; ++r) tot += sums[(sb + r) * kSampleValues + li];
+                const double corr = (li < 3) ? (double)n : (li >= 6 && li < 9) ? (double)z2 : 0.0;
+                if (valid) {
+                    const int64_t q = (g + 1) / a.sample_every - g0 / a.sample_every - 1;
+                    a.samples[(q * a.n_chains + chain) * kSampleValues + li] = tot - corr;
+                }
             }
-            if (valid && li == 0) {
-                const int64_t q = (g + 1) / a.sample_every - g0 / a.sample_every - 1;
-                double* out = a.samples + (q * a.n_chains + chain) * kSampleValues;
-                out[0] = p[0] - n;
-                out[1] = p[1] - n;
-                out[2] = p[2] - n;
-                out[3] = p[3];
-                out[4] = p[4];
-                out[5] = p[5];
-                out[6] = p[6] - z2;
-                out[7] = p[7] - z2;
-                out[8] = p[8] - z2;
-                out[9] = p[9];
-                out[10] = p[10];
-                out[11] = p[11];
-            }
+            wave_sync();  // the records are rewritten by the next step
         }
     }
 

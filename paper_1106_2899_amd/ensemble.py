@@ -219,6 +219,11 @@ class Ensemble:
         self.stream.synchronize()
         return out
 
+    def set_mapping(self, n_lo: int, n_hi: int, lanes_per_chain: int, beads_per_lane: int) -> "Ensemble":
+        """Chain-to-wavefront mapping for chains with n_lo <= N <= n_hi."""
+        self._chk(lib().ssp_set_mapping(self._h, int(n_lo), int(n_hi), int(lanes_per_chain), int(beads_per_lane)))
+        return self
+
     def set_kernel_timing(self, enable: bool) -> "Ensemble":
         self._chk(lib().ssp_set_kernel_timing(self._h, 1 if enable else 0))
         return self

@@ -155,3 +155,33 @@ def test_nonfinite_state_is_reported():
     with pytest.raises(SspError) as ei:
         e.stress()
     assert ei.value.code == -4
+
+
+def test_trajectory_does_not_depend_on_the_mapping():
+    N = [20, 24, 31, 17] * 16
+    kap = [[0, 0.4, 0], [0, 0, 0], [0, 0, 0]]
+    ref = None
+    for W, B in [(32, 1), (64, 1), (16, 2), (32, 2), (64, 2)]:
+        e = _ens(N, precision="fp32", seed=21, corr_levels=0)
+        e.set_mapping(17, 31, W, B)
+        e.init().step(150, kap)
+        st = [x.cpu() for x in e.state()]
+        if ref is None:
+            ref = st
+        else:
+            for x, y in zip(ref, st):
+                assert torch.equal(x, y), (W, B)
+        e.close()
+
+
+def test_autotuner_picks_a_valid_mapping_and_keeps_results():
+    from paper_1106_2899_amd import autotune
+    N = np.array([12, 30, 50, 100] * 64, dtype=np.int32)
+    e = _ens(N, precision="fp32", seed=22, corr_levels=0)
+    res = autotune.tune(e, steps=50, probe_chains=256)
+    for (lo, hi), (W, B) in res.choices.items():
+        assert W * B >= N[(N >= lo) & (N <= hi)].max()
+    e.init().step(100)
+    f = _ens(N, precision="fp32", seed=22, corr_levels=0).init().step(100)
+    for x, y in zip(e.state(), f.state()):
+        assert torch.equal(x, y)
