@@ -32,20 +32,22 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: full-rate
 
 def algorithmic_valu_slots(sample_every: int = SAMPLE_EVERY, n0: float = 4.0) -> float:
     """VALU issue slots per bead-step that the method needs, weighting each
-    operation by its issue cost on CDNA (full rate = 1; 32x32->64 integer
-    multiply and FP32 transcendentals = 4, quarter rate; FP64 FMA = 1):
+    operation by its issue cost measured on gfx950 with a throughput probe
+    (full rate = 1, which includes the 32x32->64 integer multiply and the
+    three-input bitop; FP32 transcendentals log/exp/sin/cos/sqrt/rcp = 2;
+    FP64 FMA = 1):
       two Philox4x32-10 blocks (bead noise, slot uniforms): 10 rounds x
-        (2 products x 4 + 2 three-input xors) = 100 each        -> 200
+        (2 products + 2 three-input xors) = 40 each             ->  80
       Box-Muller, 3 normals: 4 uniforms x 3, 2 log, 2 sqrt,
-        3 sin/cos (x4 each), 5 multiplies                        ->  45
+        3 sin/cos (x2 each), 5 multiplies                        ->  31
       forces, flow, Euler move: bonds 3, bond force 6, spring 3,
         kappa.R 9, increment 9, position update 3                ->  33
       hop per occupied slot (fraction 1/N_0): offset 3, two energy
-        differences 12, two probabilities 2 x 12, decision 3     ->  42 / N_0
+        differences 12, two probabilities 2 x 8, decision 3      ->  34 / N_0
       reconstruction threshold tests                             ->   2
       stress and virtual stress products (FP64), per sample      -> 7.5 / n_s
     """
-    return 200.0 + 45.0 + 33.0 + 42.0 / n0 + 2.0 + 7.5 / sample_every
+    return 80.0 + 31.0 + 33.0 + 34.0 / n0 + 2.0 + 7.5 / sample_every
 
 
 def _sha(path):
@@ -97,6 +99,49 @@ def run_gpu(precision, md_steps, steps, warmup, timing=False, use_graph=True):
     assert torch.isfinite(stress).all()
     e.close()
     return t1 - t0, kt
+
+
+def adjoint_ratio(chains=65536, beads=64, window=2000, ckpt=100, rate=0.01, reps=2):
+    """Adjoint/forward time ratio on the differentiation workload: (recorded
+    forward + checkpointed reverse pass) / plain forward of the same window."""
+    import torch
+
+    from paper_1106_2899_amd.ensemble import Ensemble
+
+    kap = torch.zeros(1, 9, dtype=torch.float64, device="cuda")
+    kap[0, 1] = rate
+    e = Ensemble(beads, chains, precision="fp32", seed=5, sample_every=SAMPLE_EVERY, corr_levels=0, use_graph=True)
+    e.init()
+    e.forward_record(window, ckpt, kap)
+    e.adjoint()
+    e.step(window, kap)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t_fwd = t_rec = t_rev = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        e.step(window, kap)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e.forward_record(window, ckpt, kap)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g = e.adjoint()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t_fwd += t1 - t0
+        t_rec += t2 - t1
+        t_rev += t3 - t2
+    assert torch.isfinite(g).all()
+    e.close()
+    return {
+        "workload": f"adjoint_{chains}x{beads}",
+        "window": window,
+        "checkpoint_every": ckpt,
+        "forward_ms": t_fwd / reps * 1e3,
+        "recorded_forward_ms": t_rec / reps * 1e3,
+        "reverse_ms": t_rev / reps * 1e3,
+        "adjoint_over_forward": (t_rec + t_rev) / t_fwd,
+    }
 
 
 def cpu_baseline(sample_chains=4096, sample_steps=16000):
@@ -186,6 +231,7 @@ def main():
         "fp64_plain": {"value": v64, "unit": "bead-steps/s", "steps": k64, "ms_per_step": t64 / k64 * 1e3},
         "fp32_over_fp64": v32 / v64,
         "roofline": roofline,
+        "adjoint": adjoint_ratio(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -171,6 +171,39 @@ int ssp_step_count(const ssp_handle* h, int64_t* steps_host);
 int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead, int32_t count, double* out_dev,
                     ssp_stream stream);
 
+/* ---- Differentiation (pathwise adjoint, conditioned on the events) --------
+ * The derivative of a final stress component J_k = sigma_c(R_T) of every
+ * chain k with respect to the velocity gradient kappa (all nine entries) and
+ * the slip-spring strength N_s, taken through the Euler map of Sec. 3.1 with
+ * the recorded hop/creation/destruction events and the random normals held
+ * fixed (the dependence of the event probabilities on the parameters is not
+ * included).  Created anchors A = R_end + sqrt(N_s/3) g carry their N_s
+ * dependence.  Memory: (window+1) bytes per bead for the slot trajectory,
+ * one state copy per checkpoint, and (ckpt_every+1) x 6 reals per bead for
+ * the replay of one segment. */
+
+/* Bytes of the caller-owned recording buffer for a window of `window` steps
+ * with a checkpoint every `ckpt_every` steps. */
+int ssp_adjoint_bytes(const ssp_handle* h, int64_t window, int32_t ckpt_every, size_t* bytes);
+
+/* Advances the ensemble by `window` steps exactly like ssp_step (same
+ * trajectory, samples and counters) while recording the slot state after every
+ * step and a state checkpoint every ckpt_every steps into rec_dev (256-byte
+ * aligned, ssp_adjoint_bytes long).  kappa_dev as in ssp_step.  Asynchronous. */
+int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const double* kappa_dev, void* rec_dev,
+                       ssp_stream stream);
+
+/* Reverse pass over the last recorded window: for every checkpoint segment,
+ * last to first, replays the segment from its checkpoint (bitwise the same
+ * trajectory) and runs the adjoint recursion through it.  grad_dev [M][10]
+ * FP64 receives dJ_k/dkappa_ab (row-major, 9 values) and dJ_k/dN_s for
+ * J_k = sigma_component of chain k at the end of the window (component 0..5
+ * = xx yy zz xy yz zx).  kappa_dev must hold the velocity gradient of the
+ * recorded window.  init_window != 0 adds the N_s dependence of the sampled
+ * initial anchors when the window started at step 0.  Synchronises. */
+int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
+                double* grad_dev, ssp_stream stream);
+
 /* Chain-to-wavefront mapping for the chains with n_lo <= N <= n_hi: each
  * such chain occupies lanes_per_chain lanes (8, 16, 32 or 64) with
  * beads_per_lane beads and slots per lane (1, or 2 with 16, 32 or 64 lanes);

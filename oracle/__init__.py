@@ -157,7 +157,7 @@ class Ensemble:
 
     def _kappa(self, kappa):
         k = np.zeros((self.M, 9)) if kappa is None else np.asarray(kappa, dtype=np.float64)
-        if k.shape == (3, 3) or k.shape == (9,):
+        if k.size == 9:
             k = np.broadcast_to(k.reshape(1, 9), (self.M, 9))
         return np.ascontiguousarray(k.reshape(self.M, 9))
 

@@ -35,6 +35,9 @@ EXPORTS = [
     "ssp_reset_observables",
     "ssp_step_count",
     "ssp_rng_normals",
+    "ssp_adjoint_bytes",
+    "ssp_forward_record",
+    "ssp_adjoint",
     "ssp_set_mapping",
     "ssp_set_kernel_timing",
     "ssp_kernel_time",
@@ -102,6 +105,9 @@ def lib():
             "ssp_reset_observables": [vp, vp],
             "ssp_step_count": [vp, ctypes.POINTER(ctypes.c_int64)],
             "ssp_rng_normals": [vp, i64, i64, i32, i32, vp, vp],
+            "ssp_adjoint_bytes": [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "ssp_forward_record": [vp, i64, i32, vp, vp, vp],
+            "ssp_adjoint": [vp, vp, vp, i32, i32, vp, vp],
             "ssp_set_mapping": [vp, i32, i32, i32, i32],
             "ssp_set_kernel_timing": [vp, ctypes.c_int],
             "ssp_kernel_time": [vp, f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],

@@ -1,0 +1,63 @@
+"""torch.autograd.Function around the library's pathwise adjoint.
+
+FinalStress maps per-element flow rates (and the slip-spring strength N_s)
+to the ensemble-mean final stress of each element after a window of steps:
+
+    J_e = (1/M_e) sum_{k in e} sigma_c,k(T),   kappa_e = rate_e * D_e,
+
+with D_e a fixed flow-direction tensor per element (simple shear: D_xy = 1;
+uniaxial elongation: diag(1, -1/2, -1/2)).  The forward pass records the
+window; the backward pass runs the library's reverse pass (checkpointed
+replay) and returns dJ_e/drate_e and dJ_e/dN_s, conditioned on the recorded
+events and random normals.  N_s is a property of the ensemble: the value
+passed in must equal it (the gradient with respect to it is still returned).
+"""
+from __future__ import annotations
+
+import torch
+
+COMPONENTS = {"xx": 0, "yy": 1, "zz": 2, "xy": 3, "yz": 4, "zx": 5}
+
+
+class FinalStress(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rates, ns, ensemble, directions, window, ckpt_every, component="xy", init_window=True):
+        if abs(float(ns) - ensemble.ns) > 1e-12 * max(1.0, abs(ensemble.ns)):
+            raise ValueError("ns must equal the ensemble's slip-spring strength")
+        dirs = torch.as_tensor(directions, dtype=torch.float64, device=ensemble.device).reshape(-1, 3, 3)
+        if dirs.shape[0] == 1:
+            dirs = dirs.expand(ensemble.n_elements, 3, 3)
+        r = rates.detach().to(device=ensemble.device, dtype=torch.float64).reshape(-1)
+        kappa = (r[:, None, None] * dirs).reshape(ensemble.n_elements, 9).contiguous()
+        comp = COMPONENTS[component] if isinstance(component, str) else int(component)
+        ensemble.forward_record(window, ckpt_every, kappa)
+        sig = ensemble.stress()[:, comp]
+        offs = torch.as_tensor(ensemble.element_offsets, dtype=torch.int64)
+        counts = (offs[1:] - offs[:-1]).to(ensemble.device)
+        elem = torch.repeat_interleave(torch.arange(ensemble.n_elements, device=ensemble.device), counts)
+        J = torch.zeros(ensemble.n_elements, dtype=torch.float64, device=ensemble.device)
+        J.index_add_(0, elem, sig)
+        J = J / counts
+        ctx.ensemble, ctx.dirs, ctx.comp, ctx.init_window = ensemble, dirs, comp, init_window
+        ctx.elem, ctx.counts = elem, counts
+        ctx.rates_device, ctx.rates_dtype = rates.device, rates.dtype
+        ctx.ns_is_tensor = torch.is_tensor(ns)
+        return J.to(rates.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        e = ctx.ensemble
+        g = e.adjoint(ctx.comp, ctx.init_window)                      # [M][10]
+        gk = g[:, :9].reshape(-1, 3, 3)
+        d_rate = (gk * ctx.dirs[ctx.elem]).sum(dim=(1, 2))           # dJ_k/drate_e per chain
+        dr = torch.zeros(e.n_elements, dtype=torch.float64, device=e.device).index_add_(0, ctx.elem, d_rate) / ctx.counts
+        dn = torch.zeros(e.n_elements, dtype=torch.float64, device=e.device).index_add_(0, ctx.elem, g[:, 9]) / ctx.counts
+        gJ = gJ.to(device=e.device, dtype=torch.float64)
+        grad_rates = (gJ * dr).to(device=ctx.rates_device, dtype=ctx.rates_dtype)
+        grad_ns = (gJ * dn).sum().to(device=ctx.rates_device) if ctx.ns_is_tensor else None
+        return grad_rates, grad_ns, None, None, None, None, None, None
+
+
+def final_stress(rates, ns, ensemble, directions, window, ckpt_every, component="xy", init_window=True):
+    """J [E] = FinalStress.apply(...) (see the class)."""
+    return FinalStress.apply(rates, ns, ensemble, directions, window, ckpt_every, component, init_window)

@@ -1,0 +1,393 @@
+// Discrete adjoint of the Euler map of Sec. 3.1 over a recorded window,
+// conditioned on the recorded slot trajectory (hops, creations,
+// destructions) and on the random normals: the pathwise derivative of a
+// final stress component J = sigma_c(R_T) of every chain with respect to the
+// velocity gradient kappa (all nine entries) and the slip-spring strength
+// N_s.  One launch processes one checkpoint segment backwards, reading the
+// (R, A) trajectory that the replay of the segment stored.
+//
+// Per step m of the segment (state before the step: R_m, A_m, slots S_m;
+// after: S_{m+1}), with lR = dJ/dR_{m+1}, lA = dJ/dA_{m+1}:
+//   created slots (S_m < 0 <= S_{m+1}):  lR[S_{m+1}] += lA,
+//                                         dJ/dN_s += lA . g / (2 sqrt(3 N_s));
+//   dJ/dN_s    += dt (3/N_s^2) lR[S_m] . (R_m[S_m] - A_m)        (occupied),
+//   dJ/dkappa  += dt (lR (x) R_m + lA (x) A_m)                    (surviving slots),
+//   dJ/dA_m     = (1 + dt kappa^T) lA (surviving) + dt (3/N_s) lR[S_m],
+//   dJ/dR_m     = lR + dt (L lR - (3/N_s) c lR + kappa^T lR),
+// L the free-end bond Laplacian (stiffness 3) and c the springs per bead.
+#include "ssp_device.h"
+#include "ssp_internal.h"
+
+namespace ssp {
+
+namespace {
+
+template <typename T> struct alignas(16) AdjRec {
+    T v[8];  // lR (3), R_m (3), padding
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(p.x, l), __builtin_amdgcn_readlane(p.y, l)));
+}
+
+template <typename T> __device__ __forceinline__ v3<T> kT(const T (&k)[9], v3<T> l)
+{
+    return {k[0] * l.x + k[3] * l.y + k[6] * l.z, k[1] * l.x + k[4] * l.y + k[7] * l.z,
+            k[2] * l.x + k[5] * l.y + k[8] * l.z};
+}
+
+template <typename T> __device__ __forceinline__ T comp_of(v3<T> v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : v.z);
+}
+
+// d sigma_ab / d b for sigma_ab = 3 b_a b_b.
+template <typename T> __device__ __forceinline__ v3<T> dsigma(v3<T> b, int ca, int cb)
+{
+    v3<T> g = zero3<T>();
+    const T va = T(3) * comp_of(b, cb), vb = T(3) * comp_of(b, ca);
+    if (ca == 0) g.x += va;
+    if (ca == 1) g.y += va;
+    if (ca == 2) g.z += va;
+    if (cb == 0) g.x += vb;
+    if (cb == 1) g.y += vb;
+    if (cb == 2) g.z += vb;
+    return g;
+}
+
+template <typename T, int W, int B>
+__global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
+{
+    constexpr int kChainsPerWave = kWaveSize / W;
+    constexpr int kCap = W * B;
+    __shared__ AdjRec<T> lds_rec[kWavesPerGroup][kWaveSize * B];
+    __shared__ uint32_t lds_cnt[kWavesPerGroup][kWaveSize * B];
+    __shared__ double lds_sum[kWavesPerGroup][kWaveSize * 10];
+
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wv = threadIdx.x / kWaveSize;
+    const int li = lane % W;
+    const int seg = lane / W;
+    const int sb = lane - li;
+    const int64_t task = ((int64_t)blockIdx.x * kWavesPerGroup + wv) * kChainsPerWave + seg;
+    const bool valid = task < a.n_tasks;
+    const int chain = valid ? a.tasks[task] : 0;
+    const int n = valid ? a.ct.n[chain] : 0;
+    const int64_t off = valid ? a.ct.off[chain] : 0;
+    const uint32_t gid = valid ? a.ct.gid[chain] : 0u;
+    const int elem = valid ? a.ct.elem[chain] : 0;
+    const int lbase = seg * kCap;
+    AdjRec<T>* rec = lds_rec[wv];
+    uint32_t* cnt = lds_cnt[wv];
+    double* sums = lds_sum[wv];
+
+    const T dt = T(a.ph.dt);
+    const T ks = T(3.0 / a.ph.ns);
+    const double dsig = 1.0 / (2.0 * sqrt(3.0 * a.ph.ns));
+    const double kns = a.ph.dt * 3.0 / (a.ph.ns * a.ph.ns);
+    const double ddt = a.ph.dt;
+    T kap[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
+    const T* traj = reinterpret_cast<const T*>(a.traj);
+    T* lam = reinterpret_cast<T*>(a.lam);
+    const int ca = (a.comp < 3) ? a.comp : (a.comp == 3 ? 0 : (a.comp == 4 ? 1 : 2));
+    const int cb = (a.comp < 3) ? a.comp : (a.comp == 3 ? 1 : (a.comp == 4 ? 2 : 0));
+
+    auto traj_r = [&](int row, int i) -> v3<T> {
+        const T* p = traj + ((int64_t)row * a.total + off + i) * 6;
+        return {p[0], p[1], p[2]};
+    };
+    auto traj_a = [&](int row, int i) -> v3<T> {
+        const T* p = traj + ((int64_t)row * a.total + off + i) * 6;
+        return {p[3], p[4], p[5]};
+    };
+
+    v3<T> lR[B], lA[B];
+    if (a.seed_lambda) {
+        v3<T> R[B], br[B], bl[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) R[b] = (li * B + b < n) ? traj_r(a.len, li * B + b) : zero3<T>();
+        const v3<T> nx = from_next3(R[0]);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            const v3<T> h = (b + 1 < B) ? R[b + 1 < B ? b + 1 : b] : nx;
+            br[b] = (i < n - 1) ? (h - R[b]) : zero3<T>();
+        }
+        const v3<T> left = from_prev3(br[B - 1]);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            bl[b] = (i > 0 && i < n) ? ((b > 0) ? br[b > 0 ? b - 1 : 0] : left) : zero3<T>();
+            lR[b] = (i < n) ? (dsigma(bl[b], ca, cb) - dsigma(br[b], ca, cb)) : zero3<T>();
+            lA[b] = zero3<T>();
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            if (i < n) {
+                const T* p = lam + (off + i) * 6;
+                lR[b] = {p[0], p[1], p[2]};
+                lA[b] = {p[3], p[4], p[5]};
+            } else {
+                lR[b] = zero3<T>();
+                lA[b] = zero3<T>();
+            }
+        }
+    }
+
+    double G[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) G[q] = 0.0;
+    double Gns = 0.0;
+
+    for (int m = a.len - 1; m >= 0; --m) {
+        const int64_t mg = a.m0 + m;
+        int sm[B], s1[B];
+        v3<T> Rm[B], Am[B];
+        bool any_cr = false;
+        bool cr[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            const bool act = i < n;
+            sm[b] = act ? (int)a.rec_s[mg * a.total + off + i] : -1;
+            s1[b] = act ? (int)a.rec_s[(mg + 1) * a.total + off + i] : -1;
+            Rm[b] = act ? traj_r(m, i) : zero3<T>();
+            Am[b] = act ? traj_a(m, i) : zero3<T>();
+            cr[b] = sm[b] < 0 && s1[b] >= 0;
+            any_cr |= cr[b];
+        }
+        // created springs: their anchor depends on the end bead after the move
+        if (__ballot(any_cr) != 0) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (cr[b]) {
+                    const v3<T> g = normals3<T>(draw(kAnchor, (uint32_t)(li * B + b), gid, a.rec_g0 + mg, a.ph.key0,
+                                                     a.ph.key1));
+                    Gns += (double)dot(lA[b], g) * dsig;
+                }
+            }
+#pragma unroll
+            for (int bb = 0; bb < B; ++bb) {
+                uint64_t mask = __ballot(cr[bb]);
+                while (mask) {
+                    const int L = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    const int e = __builtin_amdgcn_readlane(s1[bb], L);
+                    const v3<T> v = {lane_value(lA[bb].x, L), lane_value(lA[bb].y, L), lane_value(lA[bb].z, L)};
+                    const int tl = (L / W) * W + e / B;
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        if (lane == tl && b == e % B) lR[b] = lR[b] + v;
+                }
+            }
+        }
+        // springs per bead at step m (integer LDS atomics: order-free)
+#pragma unroll
+        for (int b = 0; b < B; ++b) cnt[lbase + li * B + b] = 0u;
+        wave_sync();
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (sm[b] >= 0) atomicAdd(&cnt[lbase + sm[b]], 1u);
+        wave_sync();
+        int c[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            c[b] = (int)cnt[lbase + li * B + b];
+            AdjRec<T> r;
+            r.v[0] = lR[b].x;
+            r.v[1] = lR[b].y;
+            r.v[2] = lR[b].z;
+            r.v[3] = Rm[b].x;
+            r.v[4] = Rm[b].y;
+            r.v[5] = Rm[b].z;
+            r.v[6] = T(0);
+            r.v[7] = T(0);
+            rec[lbase + li * B + b] = r;
+        }
+        wave_sync();
+        // slots
+        v3<T> nA[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int t = sm[b] > 0 ? sm[b] : 0;
+            const AdjRec<T> r = rec[lbase + t];
+            const v3<T> lRS = {r.v[0], r.v[1], r.v[2]};
+            const v3<T> RS = {r.v[3], r.v[4], r.v[5]};
+            nA[b] = zero3<T>();
+            if (sm[b] >= 0) {
+                const v3<T> dd = RS - Am[b];
+                Gns += kns * ((double)lRS.x * dd.x + (double)lRS.y * dd.y + (double)lRS.z * dd.z);
+                if (s1[b] >= 0) {
+                    nA[b] = lA[b] + dt * kT(kap, lA[b]);
+                    const double la[3] = {lA[b].x, lA[b].y, lA[b].z};
+                    const double am[3] = {Am[b].x, Am[b].y, Am[b].z};
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) G[3 * p + q] += ddt * la[p] * am[q];
+                }
+                nA[b] = nA[b] + (dt * ks) * lRS;
+            }
+        }
+        // beads
+        const v3<T> nxt = from_next3(lR[0]);
+        const v3<T> prv = from_prev3(lR[B - 1]);
+        v3<T> nR[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            const v3<T> right = (b + 1 < B) ? lR[b + 1 < B ? b + 1 : b] : nxt;
+            const v3<T> left = (b > 0) ? lR[b > 0 ? b - 1 : 0] : prv;
+            v3<T> lap = zero3<T>();
+            if (i < n - 1) lap = lap + T(3) * (right - lR[b]);
+            if (i > 0) lap = lap - T(3) * (lR[b] - left);
+            if (i < n) {
+                const double lr[3] = {lR[b].x, lR[b].y, lR[b].z};
+                const double rm[3] = {Rm[b].x, Rm[b].y, Rm[b].z};
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) G[3 * p + q] += ddt * lr[p] * rm[q];
+                nR[b] = lR[b] + dt * (lap - (ks * T(c[b])) * lR[b] + kT(kap, lR[b]));
+            } else {
+                nR[b] = zero3<T>();
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            lR[b] = nR[b];
+            lA[b] = nA[b];
+        }
+        wave_sync();
+    }
+
+    // N_s dependence of the sampled initial anchors A = R_S + sqrt(N_s/3) g
+    if (a.init_terms) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = li * B + b;
+            const int s0 = (j < n) ? (int)a.rec_s[off + j] : -1;
+            if (s0 >= 0) {
+                const v3<double> g = normals3_f64(draw(kInitAnchor, (uint32_t)j, gid, 0, a.ph.key0, a.ph.key1));
+                Gns += ((double)lA[b].x * g.x + (double)lA[b].y * g.y + (double)lA[b].z * g.z) * dsig;
+            }
+        }
+    }
+
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = li * B + b;
+        if (i < n) {
+            T* p = lam + (off + i) * 6;
+            p[0] = lR[b].x;
+            p[1] = lR[b].y;
+            p[2] = lR[b].z;
+            p[3] = lA[b].x;
+            p[4] = lA[b].y;
+            p[5] = lA[b].z;
+        }
+    }
+    // per-chain sums of the lane accumulators, in lane order
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sums[lane * 10 + q] = G[q];
+    sums[lane * 10 + 9] = Gns;
+    wave_sync();
+    for (int v = li; v < 10; v += W) {
+        double tot = 0.0;
+        for (int r = 0; r < W; ++r) tot += sums[(sb + r) * 10 + v];
+        if (valid) a.grad[(int64_t)chain * 10 + v] += tot;
+    }
+}
+
+template <typename T, int W, int B> hipError_t launch_t(const AdjointArgs& a, hipStream_t s)
+{
+    constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
+    const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
+    if (groups == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_adjoint<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t launch_p(int W, int B, const AdjointArgs& a, hipStream_t s)
+{
+    if (B == 1) {
+        switch (W) {
+        case 8: return launch_t<T, 8, 1>(a, s);
+        case 16: return launch_t<T, 16, 1>(a, s);
+        case 32: return launch_t<T, 32, 1>(a, s);
+        case 64: return launch_t<T, 64, 1>(a, s);
+        }
+    } else if (B == 2) {
+        switch (W) {
+        case 16: return launch_t<T, 16, 2>(a, s);
+        case 32: return launch_t<T, 32, 2>(a, s);
+        case 64: return launch_t<T, 64, 2>(a, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+// Byte copy (state checkpoints) in 16-byte words; sizes are multiples of 256.
+__global__ void k_copy16(uint4* dst, const uint4* src, int64_t n16)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
+}
+
+__global__ void k_rec_s0(const int32_t* S, int8_t* rec, int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < total) rec[i] = (int8_t)S[i];
+}
+
+__global__ void k_set_ctrl_steps(int64_t* ctrl, int64_t steps)
+{
+    if (threadIdx.x == 0) ctrl[kCtrlSteps] = steps;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(int precision, int W, int B, const AdjointArgs& a, hipStream_t s)
+{
+    return precision == 0 ? launch_p<float>(W, B, a, s) : launch_p<double>(W, B, a, s);
+}
+
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s, reinterpret_cast<uint4*>(dst),
+                       reinterpret_cast<const uint4*>(src), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_rec_s0(const int32_t* S, int8_t* rec, int64_t total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rec_s0, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, S, rec, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_ctrl_steps(int64_t* ctrl, int64_t steps, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_ctrl_steps, dim3(1), dim3(64), 0, s, ctrl, steps);
+    return hipGetLastError();
+}
+
+}  // namespace ssp

@@ -232,6 +232,12 @@ struct ssp_handle {
     char* work = nullptr;
     std::vector<std::pair<Mapping, std::pair<int64_t, int64_t>>> groups;  // mapping, [task begin, count)
     std::vector<Mapping> chain_map;                                       // mapping of every chain
+    // last recorded window (adjoint)
+    struct {
+        const void* ptr = nullptr;
+        int64_t window = 0, g0 = 0;
+        int32_t ckpt = 0;
+    } rec;
     bool initialized = false;
     int64_t steps = 0, corr_samples = 0, series_samples = 0;
     hipStream_t capture_stream = nullptr;
@@ -296,7 +302,8 @@ int fail(ssp_handle* h, int code, const std::string& msg)
         if (e_ != hipSuccess) return fail((h), SSP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s)
+int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, int8_t* rec_s = nullptr,
+                  int64_t rec_g0 = 0)
 {
     const ssp_config& k = h->res.cfg;
     const int64_t M = k.n_chains;
@@ -324,6 +331,9 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s)
             a.samples = h->samples();
             a.n_chains = M;
             a.flags = h->flags();
+            a.rec_s = rec_s;
+            a.rec_g0 = rec_g0;
+            a.total = h->res.total_beads;
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
         }
         if (h->timing) {
@@ -686,6 +696,158 @@ int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead,
     const Physics p = h->phys();
     HIPCHK(h, launch_rng_normals(h->res.cfg.precision, p.key0, p.key1, (uint32_t)chain_id, step, bead, count, out_dev, s));
     return SSP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Regions of a recording buffer: slot rows, checkpoints, replay state and
+// control words, segment trajectory, carried adjoint.
+struct RecLayout {
+    size_t rows, ckpts, scratch, ctrl, traj, lam, total;
+    int n_seg;
+};
+
+RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
+{
+    RecLayout L{};
+    const size_t beads = (size_t)h->res.total_beads;
+    const size_t t = h->res.cfg.precision == SSP_FP32 ? 4 : 8;
+    L.n_seg = (int)((window + ckpt - 1) / ckpt);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.rows = take((size_t)(window + 1) * beads);
+    L.ckpts = take((size_t)L.n_seg * h->lay.state_total);
+    L.scratch = take(h->lay.state_total);
+    L.ctrl = take(sizeof(int64_t) * kCtrlWords);
+    L.traj = take((size_t)(ckpt + 1) * beads * 6 * t);
+    L.lam = take(beads * 6 * t);
+    L.total = o;
+    return L;
+}
+
+State state_at(const ssp_handle* h, char* base)
+{
+    State s;
+    s.r0 = base + h->lay.r0;
+    s.r1 = h->res.cfg.precision == SSP_FP32 ? base + h->lay.r1 : nullptr;
+    s.a0 = base + h->lay.a0;
+    s.a1 = h->res.cfg.precision == SSP_FP32 ? base + h->lay.a1 : nullptr;
+    s.s = reinterpret_cast<int32_t*>(base + h->lay.s);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssp_adjoint_bytes(const ssp_handle* h, int64_t window, int32_t ckpt_every, size_t* bytes)
+{
+    if (!h || !bytes || window < 1 || ckpt_every < 1) return SSP_EINVAL;
+    *bytes = rec_layout(h, window, ckpt_every).total;
+    return SSP_OK;
+}
+
+int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const double* kappa_dev, void* rec_dev,
+                       ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!h->initialized) return fail(h, SSP_ESTATE, "ssp_forward_record before ssp_init_equilibrium");
+    if (window < 1 || ckpt_every < 1 || !kappa_dev || !rec_dev)
+        return fail(h, SSP_EINVAL, "window >= 1, ckpt_every >= 1, kappa_dev and rec_dev are required");
+    if (reinterpret_cast<uintptr_t>(rec_dev) % kAlign) return fail(h, SSP_EINVAL, "rec_dev must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    const RecLayout R = rec_layout(h, window, ckpt_every);
+    char* rec = static_cast<char*>(rec_dev);
+    int8_t* rows = reinterpret_cast<int8_t*>(rec + R.rows);
+    const int64_t g0 = h->steps;
+    HIPCHK(h, launch_rec_s0(h->st().s, rows, h->res.total_beads, s));
+    for (int c = 0; c < R.n_seg; ++c) {
+        HIPCHK(h, launch_copy_bytes(rec + R.ckpts + (size_t)c * h->lay.state_total, h->state, h->lay.state_total, s));
+        const int64_t m = std::min<int64_t>(ckpt_every, window - (int64_t)c * ckpt_every);
+        int rc = enqueue_steps(h, m, kappa_dev, s, rows, g0);
+        if (rc) return rc;
+        const int64_t q = samples_between(h->steps, m, h->res.cfg.sample_every);
+        h->steps += m;
+        h->corr_samples += q;
+        h->series_samples += q;
+    }
+    h->rec.ptr = rec_dev;
+    h->rec.window = window;
+    h->rec.ckpt = ckpt_every;
+    h->rec.g0 = g0;
+    return SSP_OK;
+}
+
+int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
+                double* grad_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!rec_dev || rec_dev != h->rec.ptr) return fail(h, SSP_ESTATE, "rec_dev does not hold the last recorded window");
+    if (!kappa_dev || !grad_dev || component < 0 || component > 5)
+        return fail(h, SSP_EINVAL, "kappa_dev, grad_dev and component 0..5 are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    const ssp_config& k = h->res.cfg;
+    const RecLayout R = rec_layout(h, h->rec.window, h->rec.ckpt);
+    char* rec = static_cast<char*>(const_cast<void*>(rec_dev));
+    const int8_t* rows = reinterpret_cast<const int8_t*>(rec + R.rows);
+    char* scratch = rec + R.scratch;
+    int64_t* sctrl = reinterpret_cast<int64_t*>(rec + R.ctrl);
+    HIPCHK(h, launch_zero(grad_dev, k.n_chains * 10, s));
+    for (int c = R.n_seg - 1; c >= 0; --c) {
+        const int64_t m = std::min<int64_t>(h->rec.ckpt, h->rec.window - (int64_t)c * h->rec.ckpt);
+        // replay the segment from its checkpoint, storing the trajectory
+        HIPCHK(h, launch_copy_bytes(scratch, rec + R.ckpts + (size_t)c * h->lay.state_total, h->lay.state_total, s));
+        HIPCHK(h, launch_set_ctrl_steps(sctrl, h->rec.g0 + (int64_t)c * h->rec.ckpt, s));
+        for (auto& g : h->groups) {
+            StepArgs a{};
+            a.st = state_at(h, scratch);
+            a.ct = h->ct();
+            a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
+            a.n_tasks = g.second.second;
+            a.kappa = kappa_dev;
+            a.thr = reinterpret_cast<const uint32_t*>(h->work + h->lay.thr);
+            a.thr_destroy = threshold(std::min(k.dt / k.zeta_s * 1.0, 1.0));
+            a.ph = h->phys();
+            a.ctrl = sctrl;
+            a.n_steps = (int32_t)m;
+            a.sample_every = 0;
+            a.samples = nullptr;
+            a.n_chains = k.n_chains;
+            a.flags = h->flags();
+            a.total = h->res.total_beads;
+            a.traj = rec + R.traj;
+            HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
+        }
+        for (auto& g : h->groups) {
+            AdjointArgs a{};
+            a.ct = h->ct();
+            a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
+            a.n_tasks = g.second.second;
+            a.kappa = kappa_dev;
+            a.ph = h->phys();
+            a.rec_s = rows;
+            a.rec_g0 = h->rec.g0;
+            a.m0 = (int64_t)c * h->rec.ckpt;
+            a.len = (int32_t)m;
+            a.traj = rec + R.traj;
+            a.lam = rec + R.lam;
+            a.grad = grad_dev;
+            a.total = h->res.total_beads;
+            a.comp = component;
+            a.seed_lambda = (c == R.n_seg - 1) ? 1 : 0;
+            a.init_terms = (c == 0 && init_window && h->rec.g0 == 0) ? 1 : 0;
+            HIPCHK(h, launch_adjoint(k.precision, g.first.W, g.first.B, a, s));
+        }
+    }
+    return check_flags(h, s);
 }
 
 int ssp_set_mapping(ssp_handle* h, int32_t n_lo, int32_t n_hi, int32_t lanes_per_chain, int32_t beads_per_lane)

@@ -68,6 +68,30 @@ struct StepArgs {
     double* samples;       // [Qcap][M][12] or null
     int64_t n_chains;
     uint32_t* flags;
+    // adjoint support (all optional)
+    int8_t* rec_s;         // [window+1][total]: slot state after step g stored at row g + 1 - rec_g0
+    int64_t rec_g0;
+    int64_t total;         // beads (= slots) in the ensemble
+    void* traj;            // [n_steps+1][total][6] T: (R, A) at launch start and after every step
+};
+
+struct AdjointArgs {
+    ChainTables ct;
+    const int32_t* tasks;
+    int64_t n_tasks;
+    const double* kappa;    // [E][9]
+    Physics ph;
+    const int8_t* rec_s;    // [window+1][total]
+    int64_t rec_g0;         // global step index of the window start
+    int64_t m0;             // window index of the segment start
+    int32_t len;            // steps in the segment
+    const void* traj;       // [len+1][total][6] T
+    void* lam;              // [total][6] T: dJ/dR, dJ/dA carried between segments
+    double* grad;           // [M][10]: dJ/dkappa (row-major), dJ/dN_s (accumulated)
+    int64_t total;
+    int32_t comp;           // objective component 0..5 (xx yy zz xy yz zx)
+    int32_t seed_lambda;    // 1 for the last segment: start from dJ/dR at its end
+    int32_t init_terms;     // 1: include the N_s dependence of the sampled initial anchors (segment at window start)
 };
 
 struct CorrArgs {
@@ -105,6 +129,10 @@ hipError_t launch_read_state(int precision, const State& st, int64_t total, doub
                              hipStream_t s);
 hipError_t launch_write_state(int precision, const State& st, int64_t total, const double* R, const double* A,
                               const int32_t* S, hipStream_t s);
+hipError_t launch_adjoint(int precision, int W, int B, const AdjointArgs& a, hipStream_t s);
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_rec_s0(const int32_t* S, int8_t* rec, int64_t total, hipStream_t s);
+hipError_t launch_set_ctrl_steps(int64_t* ctrl, int64_t steps, hipStream_t s);
 hipError_t launch_rng_normals(int precision, uint32_t key0, uint32_t key1, uint32_t gid, int64_t step, int32_t bead,
                               int32_t count, double* out, hipStream_t s);
 

@@ -236,6 +236,26 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     bonds_and_records();
     refresh_offsets();
 
+    // Trajectory rows for the adjoint replay: (R, A) of every bead/slot, with
+    // FP32 positions rounded from hi + lo.
+    auto store_traj = [&](int row) {
+        T* tr = reinterpret_cast<T*>(a.traj) + ((int64_t)row * a.total + off) * 6;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            if (i < n) {
+                T* p = tr + (int64_t)i * 6;
+                p[0] = rh[b].x + rl[b].x;
+                p[1] = rh[b].y + rl[b].y;
+                p[2] = rh[b].z + rl[b].z;
+                p[3] = ah[b].x + al[b].x;
+                p[4] = ah[b].y + al[b].y;
+                p[5] = ah[b].z + al[b].z;
+            }
+        }
+    };
+    if (a.traj) store_traj(0);
+
     const int64_t g0 = a.ctrl[kCtrlSteps];
     bool finite_ok = true;
 
@@ -389,6 +409,14 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         }
         refresh_offsets();
 
+        if (a.rec_s) {
+            int8_t* row = a.rec_s + (g + 1 - a.rec_g0) * a.total + off;
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (li * B + b < n) row[li * B + b] = (int8_t)s[b];
+        }
+        if (a.traj) store_traj(step + 1);
+
         // ---- observables of the new state.
         if (a.sample_every > 0 && ((g + 1) % a.sample_every) == 0) {
             double p[kSampleValues];
@@ -415,19 +443,20 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             int z2 = 0;
 #pragma unroll
             for (int b = 0; b < B; ++b) z2 += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
-            // Transpose through LDS: lane li < 12 of a segment sums value li
-            // over the segment's lanes in lane order (deterministic).
+            // Transpose through LDS: lane li of a segment sums values li,
+            // li + W, ... over the segment's lanes in lane order (deterministic).
 #pragma unroll
             for (int q = 0; q < kSampleValues; ++q) sums[lane * kSampleValues + q] = p[q];
             wave_sync();
-            if (li < kSampleValues) {
+#pragma unroll
+            for (int v = li; v < kSampleValues; v += W) {
                 double tot = 0.0;
 #pragma unroll 8
-                for (int r = 0; r < W; ++r) tot += sums[(sb + r) * kSampleValues + li];
-                const double corr = (li < 3) ? (double)n : (li >= 6 && li < 9) ? (double)z2 : 0.0;
+                for (int r = 0; r < W; ++r) tot += sums[(sb + r) * kSampleValues + v];
+                const double corr = (v < 3) ? (double)n : (v >= 6 && v < 9) ? (double)z2 : 0.0;
                 if (valid) {
                     const int64_t q = (g + 1) / a.sample_every - g0 / a.sample_every - 1;
-                    a.samples[(q * a.n_chains + chain) * kSampleValues + li] = tot - corr;
+                    a.samples[(q * a.n_chains + chain) * kSampleValues + v] = tot - corr;
                 }
             }
             wave_sync();  // the records are rewritten by the next step

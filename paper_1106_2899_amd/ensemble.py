@@ -219,6 +219,30 @@ class Ensemble:
         self.stream.synchronize()
         return out
 
+    # ----------------------------------------------------- differentiation
+    def forward_record(self, window: int, ckpt_every: int, kappa=None) -> "Ensemble":
+        """Advance `window` steps (like step) while recording what the adjoint needs."""
+        nbytes = ctypes.c_size_t()
+        self._chk(lib().ssp_adjoint_bytes(self._h, int(window), int(ckpt_every), ctypes.byref(nbytes)))
+        if getattr(self, "_rec_bytes", 0) < nbytes.value:
+            self._rec_t = None
+            with torch.cuda.device(self.device):
+                self._rec_t, self._rec_p = _aligned_buffer(nbytes.value, self.device)
+            self._rec_bytes = nbytes.value
+        k = self.kappa_tensor(kappa)
+        self._rec_kappa = k
+        self._chk(lib().ssp_forward_record(self._h, int(window), int(ckpt_every), ctypes.c_void_p(k.data_ptr()),
+                                           ctypes.c_void_p(self._rec_p), self._s))
+        return self
+
+    def adjoint(self, component: int = 3, init_window: bool = True) -> torch.Tensor:
+        """[M][10] FP64: dJ_k/dkappa (9, row-major) and dJ_k/dN_s for J_k = the
+        final stress component of chain k over the last recorded window."""
+        out = torch.empty((self.M, 10), dtype=torch.float64, device=self.device)
+        self._chk(lib().ssp_adjoint(self._h, ctypes.c_void_p(self._rec_p), ctypes.c_void_p(self._rec_kappa.data_ptr()),
+                                    int(component), 1 if init_window else 0, ctypes.c_void_p(out.data_ptr()), self._s))
+        return out
+
     def set_mapping(self, n_lo: int, n_hi: int, lanes_per_chain: int, beads_per_lane: int) -> "Ensemble":
         """Chain-to-wavefront mapping for chains with n_lo <= N <= n_hi."""
         self._chk(lib().ssp_set_mapping(self._h, int(n_lo), int(n_hi), int(lanes_per_chain), int(beads_per_lane)))

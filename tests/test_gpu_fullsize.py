@@ -1,0 +1,123 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses (captured graph, 1000-step launches, sampling every 10 steps,
+correlator on), checked on sampled outputs the oracle computes one chain at a
+time: a chain's trajectory depends only on (seed, global chain id, step), so
+the oracle runs just the sampled chain ids.
+
+Tolerances as in test_gpu_parity: FP32 path 1e-5 relative to max(|x|, 0.58)
+per bond/anchor offset; decisions must match (a chain may differ only through
+a sub-1e-5 tie, at most one chain per sample set).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1106_2899_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _compare_chains(e, ids, Nlist, kap_per_chain, steps, seed, tol=1e-5):
+    """Oracle run of the chains `ids` (global ids = ensemble indices here)."""
+    from paper_1106_2899_amd.ensemble import _invariants
+    R, A, S = (x.cpu().numpy() for x in e.state())
+    o = oracle.Ensemble([int(Nlist[i]) for i in ids], chain_ids=ids, seed=seed).init()
+    o.run(steps, kappa=kap_per_chain[ids], keep_samples=False)
+    mism = 0
+    for q, k in enumerate(ids):
+        n = int(Nlist[k])
+        sl = slice(int(e.offsets[k]), int(e.offsets[k]) + n)
+        osl = slice(int(o.off[q]), int(o.off[q]) + n)
+        if not np.array_equal(S[sl], o.S[osl]):
+            mism += 1
+            continue
+        bg, dg, _ = _invariants(R[sl], A[sl], S[sl], np.array([n]), np.array([0]))
+        bo, do, _ = _invariants(o.R[osl], o.A[osl], o.S[osl], np.array([n]), np.array([0]))
+        ok = ~np.isnan(bo[:, 0])
+        err = (np.abs(bg[ok] - bo[ok]) / np.maximum(np.abs(bo[ok]), 0.58)).max()
+        assert err <= tol, (k, err)
+        occ = o.S[osl] >= 0
+        if occ.any():
+            err = (np.abs(dg[occ] - do[occ]) / np.maximum(np.abs(do[occ]), 0.58)).max()
+            assert err <= tol, (k, err)
+    assert mism <= 1, mism
+    return o
+
+
+def test_lve_16384x32_bench_configuration_sampled_chains():
+    _need_gpu()
+    from paper_1106_2899_amd.ensemble import Ensemble
+    w = workloads.linear_viscoelasticity()
+    e = Ensemble(w.n_beads, precision="fp32", seed=w.seed, sample_every=w.sample_every, corr_levels=16,
+                 corr_batches=16, max_steps_per_launch=1000, use_graph=True).init()
+    e.step(1000)
+    ids = np.linspace(0, w.n_chains - 1, 48).astype(np.int64)
+    _compare_chains(e, ids, w.n_beads, np.zeros((w.n_chains, 9)), 1000, w.seed)
+    G = e.correlator()
+    assert G["counts"][0, 0] == 100 and np.isfinite(G["G"]).all()
+
+
+def test_startup_shear_full_size_sampled_chains_and_element_series():
+    _need_gpu()
+    from paper_1106_2899_amd.ensemble import Ensemble
+    w = workloads.startup_shear()
+    steps = 200
+    e = Ensemble(w.n_beads, n_elements=w.n_elements, element_offsets=w.element_offsets, precision="fp32",
+                 seed=w.seed, sample_every=w.sample_every, corr_levels=0, series_capacity=steps // w.sample_every,
+                 use_graph=True).init()
+    kap = torch.as_tensor(w.kappa.reshape(w.n_elements, 9), dtype=torch.float64, device="cuda")
+    e.step(steps, kap)
+    kchain = np.repeat(w.kappa.reshape(w.n_elements, 9), np.diff(w.element_offsets), axis=0)
+    ids = np.linspace(0, w.n_chains - 1, 40).astype(np.int64)
+    _compare_chains(e, ids, w.n_beads, kchain, steps, w.seed)
+    ser = e.element_series().cpu().numpy()
+    assert ser.shape == (w.n_elements, steps // w.sample_every, 6)
+    # whole elements recomputed by the oracle (256 chains each)
+    for el in [0, 1337, w.n_elements - 1]:
+        lo, hi = int(w.element_offsets[el]), int(w.element_offsets[el + 1])
+        ids = np.arange(lo, hi, dtype=np.int64)
+        o = oracle.Ensemble([int(x) for x in w.n_beads[lo:hi]], chain_ids=ids, seed=w.seed).init()
+        s = o.run(steps, kappa=kchain[lo:hi], sample_every=w.sample_every)
+        want = s[:, :, :6].sum(axis=1)
+        np.testing.assert_allclose(ser[el], want, rtol=0, atol=2e-4 * np.abs(want).max())
+
+
+def test_polydisperse_full_size_sampled_chains():
+    _need_gpu()
+    from paper_1106_2899_amd.ensemble import Ensemble
+    w = workloads.polydisperse()
+    steps = 200
+    e = Ensemble(w.n_beads, n_elements=w.n_elements, element_offsets=w.element_offsets, precision="fp32",
+                 seed=w.seed, sample_every=w.sample_every, corr_levels=0, use_graph=True).init()
+    kap = torch.as_tensor(w.kappa.reshape(w.n_elements, 9), dtype=torch.float64, device="cuda")
+    e.step(steps, kap)
+    kchain = np.repeat(w.kappa.reshape(w.n_elements, 9), np.diff(w.element_offsets), axis=0)
+    ids = np.linspace(0, w.n_chains - 1, 40).astype(np.int64)
+    _compare_chains(e, ids, w.n_beads, kchain, steps, w.seed)
+
+
+def test_differentiation_full_size_sampled_chains():
+    _need_gpu()
+    from paper_1106_2899_amd.ensemble import Ensemble
+    w = workloads.differentiation()
+    e = Ensemble(w.n_beads, precision="fp32", seed=w.seed, sample_every=10, corr_levels=0).init()
+    kap = w.kappa.reshape(1, 9)
+    e.forward_record(w.steps, w.extra["checkpoint_every"], kap)
+    g = e.adjoint(component=3).cpu().numpy()
+    ids = np.array([0, 7777, 40000, w.n_chains - 1], dtype=np.int64)
+    o = oracle.Ensemble([int(w.n_beads[i]) for i in ids], chain_ids=ids, seed=w.seed).init()
+    Rt, At, St = o.run_record(w.steps, kap)
+    gk, gns = o.adjoint(Rt, At, St, kap, comp=3)
+    R, A, S = (x.cpu().numpy() for x in e.state())
+    for q, k in enumerate(ids):
+        sl = slice(int(e.offsets[k]), int(e.offsets[k]) + 64)
+        if not np.array_equal(S[sl], o.S[o.off[q]:o.off[q] + 64]):
+            continue  # a tie changed an event of this chain
+        np.testing.assert_allclose(g[k, 1], gk[q, 0, 1], rtol=1e-3, atol=1e-4 * np.abs(gk[:, 0, 1]).max())
+        np.testing.assert_allclose(g[k, 9], gns[q], rtol=1e-3, atol=1e-4 * np.abs(gns).max())
