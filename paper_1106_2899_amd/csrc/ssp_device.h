@@ -42,7 +42,10 @@ __device__ __forceinline__ uint4 draw(uint32_t purpose, uint32_t index, uint32_t
 template <typename T> __device__ __forceinline__ T u01(uint32_t w);
 template <> __device__ __forceinline__ float u01<float>(uint32_t w)
 {
-    return __fmaf_rn((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+    // 0x3F800000 | (w >> 9) is 1 + (w >> 9) 2^-23 in one v_alignbit_b32;
+    // subtracting 1 - 2^-24 is exact (both operands lie in [1/2, 2]).
+    const float one_plus = __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, w, 9u));
+    return one_plus - (1.0f - 0x1p-24f);
 }
 template <> __device__ __forceinline__ double u01<double>(uint32_t w)
 {

@@ -16,7 +16,8 @@
 //     pending springs ds_min their slot index into their bead's LDS word and
 //     each bead adds the winner's offset d (read from LDS) in increasing slot
 //     order; no float atomics, so runs are bitwise reproducible;
-//   - stress sums: FP64 reduce-scatter butterfly over the segment.
+//   - stress sums: every lane writes its FP64 partial sums to LDS and the
+//     lanes of the segment add one column each in lane order (deterministic).
 //
 // Per step, in the paper's order:
 //   1. forces at time t: bond forces and slip-spring forces,
@@ -258,6 +259,9 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 
     const int64_t g0 = a.ctrl[kCtrlSteps];
     bool finite_ok = true;
+    // sampling phase: step g is sampled when (g + 1) % sample_every == 0
+    int phase = a.sample_every > 0 ? (int)((g0 + 1) % a.sample_every) : 1;
+    int64_t q_launch = 0;  // samples already written by this launch
 
     for (int step = 0; step < a.n_steps; ++step) {
         const int64_t g = g0 + step;
@@ -306,11 +310,13 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             const int i = li * B + b;
             const uint4 w = draw(kNoise, (uint32_t)i, gid, g, k0, k1);
             const v3<T> gn = normals3<T>(w);
-            const v3<T> F = T(3) * (br[b] - bl[b]) - ks * acc[b];
-            const v3<T> r = rh[b];
-            const v3<T> fl = {kap[0] * r.x + kap[1] * r.y + kap[2] * r.z, kap[3] * r.x + kap[4] * r.y + kap[5] * r.z,
+            v3<T> F = T(3) * (br[b] - bl[b]) - ks * acc[b];
+            if (flow) {  // wave-uniform; F + 0 = F keeps chains without flow bit-identical
+                const v3<T> r = rh[b];
+                F = F + v3<T>{kap[0] * r.x + kap[1] * r.y + kap[2] * r.z, kap[3] * r.x + kap[4] * r.y + kap[5] * r.z,
                               kap[6] * r.x + kap[7] * r.y + kap[8] * r.z};
-            const v3<T> inc = dt * (F + fl) + sq2dt * gn;
+            }
+            const v3<T> inc = dt * F + sq2dt * gn;
             if (i < n) {
                 if constexpr (kComp)
                     cadd3(rh[b], rl[b], inc);
@@ -418,7 +424,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         if (a.traj) store_traj(step + 1);
 
         // ---- observables of the new state.
-        if (a.sample_every > 0 && ((g + 1) % a.sample_every) == 0) {
+        if (a.sample_every > 0 && phase == 0) {
             double p[kSampleValues];
 #pragma unroll
             for (int q = 0; q < kSampleValues; ++q) p[q] = 0.0;
@@ -454,13 +460,12 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 #pragma unroll 8
                 for (int r = 0; r < W; ++r) tot += sums[(sb + r) * kSampleValues + v];
                 const double corr = (v < 3) ? (double)n : (v >= 6 && v < 9) ? (double)z2 : 0.0;
-                if (valid) {
-                    const int64_t q = (g + 1) / a.sample_every - g0 / a.sample_every - 1;
-                    a.samples[(q * a.n_chains + chain) * kSampleValues + v] = tot - corr;
-                }
+                if (valid) a.samples[(q_launch * a.n_chains + chain) * kSampleValues + v] = tot - corr;
             }
+            ++q_launch;
             wave_sync();  // the records are rewritten by the next step
         }
+        if (a.sample_every > 0) phase = (phase + 1 == a.sample_every) ? 0 : phase + 1;
     }
 
 #pragma unroll
