@@ -4,9 +4,10 @@ Workload: the equilibrium linear-viscoelasticity ensemble, 16384 chains of
 N = 32 beads (N_0 = 4, N_s = 0.5, zeta_s = 0.1, dt = 0.01), FP32 bead dynamics
 with FP64 stress, stress sampled every 10 steps into the FP64 multiple-tau
 correlator (16 levels x 16 lags).  One benchmark step is one ssp_step call of
-1000 time steps over the whole ensemble (every row of the hot path: RNG,
+5000 time steps over the whole ensemble (every row of the hot path: RNG,
 forces, Euler move, hops, reconstruction, stress, correlator), replayed from a
-captured hipGraph.  Inputs are resident in HBM before the timed region.
+captured hipGraph; the default 20 steps are the full 1e5-step run.  Inputs are
+resident in HBM before the timed region.
 
 Printed: one JSON line with bead-steps/s of the batched FP32 path, the plain
 FP64 path at the same shape, the VALU roofline of the step kernel (measured
@@ -26,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 CHAINS, BEADS, SAMPLE_EVERY = 16384, 32, 10
-MD_STEPS_PER_BENCH_STEP = 1000
+MD_STEPS_PER_BENCH_STEP = 5000  # 20 bench steps = the whole 1e5-step run
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: full-rate VALU lane-issue slots/s
 
 

@@ -1,6 +1,6 @@
 """Short, fixed GPU runs for rocprofv3 (kernel trace and counter passes).
 
-    python -m paper_1106_2899_amd.profile_run step   # step kernel, 16384 x N=32, 3 launches of 1000 steps
+    python -m paper_1106_2899_amd.profile_run step   # step kernel, 16384 x N=32, 3 launches of 5000 steps
     python -m paper_1106_2899_amd.profile_run copy   # 1 GiB read + 1 GiB write elementwise copy (counter calibration)
 """
 from __future__ import annotations
@@ -10,7 +10,7 @@ import sys
 import torch
 
 
-def step(launches: int = 3, md_steps: int = 1000) -> None:
+def step(launches: int = 3, md_steps: int = 5000) -> None:
     from .ensemble import Ensemble
 
     e = Ensemble(32, 16384, precision="fp32", seed=2, sample_every=10, corr_levels=16, corr_batches=16,
