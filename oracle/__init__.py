@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "ssp_oracle.c")
 _LIB = os.path.join(_HERE, "libssp_oracle.so")
 
 # Philox counter purposes (index | purpose << 16 in the first counter word).
-P_INIT_BOND, P_INIT_Z, P_INIT_S, P_INIT_ANCHOR, P_NOISE, P_SLOT, P_ANCHOR = 1, 2, 3, 4, 5, 6, 7
+P_INIT_BOND, P_INIT_Z, P_INIT_S, P_INIT_ANCHOR, P_NOISE, P_SLOT, P_ANCHOR, P_NOISE2 = 1, 2, 3, 4, 5, 6, 7, 8
 
 # Event bits reported per slot by a single step.
 EV_HOP_UP, EV_HOP_DOWN, EV_DESTROY, EV_CREATE_FIRST, EV_CREATE_LAST = 1, 2, 4, 8, 16
@@ -54,6 +54,8 @@ def lib():
         L.ssp_oracle_u01.restype = ctypes.c_double
         L.ssp_oracle_normals3.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, f64p]
         L.ssp_oracle_block.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, u32p]
+        L.ssp_oracle_step_noise.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, f64p]
+        L.ssp_oracle_slot_words.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, u32p]
         L.ssp_oracle_hop_prob.argtypes = [ctypes.c_int, f64p, f64p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.ssp_oracle_hop_prob.restype = ctypes.c_double
         L.ssp_oracle_init.argtypes = [ctypes.c_int, i32p, i64p, i64p, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, f64p, f64p, i32p]
@@ -106,6 +108,20 @@ def block(seed, purpose, index, chain, step):
 def normals3(seed, purpose, index, chain, step):
     out = np.zeros(3)
     lib().ssp_oracle_normals3(seed, purpose, index, chain, step, _p(out, ctypes.c_double))
+    return out
+
+
+def step_noise(seed, index, chain, step):
+    """Noise normals of bead `index` at time step `step` (step-pair layout)."""
+    out = np.zeros(3)
+    lib().ssp_oracle_step_noise(seed, index, chain, step, _p(out, ctypes.c_double))
+    return out
+
+
+def slot_words(seed, index, chain, step):
+    """(hop word, reconstruction word) of slot `index` at time step `step`."""
+    out = np.zeros(2, dtype=np.uint32)
+    lib().ssp_oracle_slot_words(seed, index, chain, step, _p(out, ctypes.c_uint32))
     return out
 
 

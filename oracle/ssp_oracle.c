@@ -43,6 +43,16 @@
  * Box-Muller transform r = sqrt(-2 ln u_a), theta = 2 pi u_b,
  * (r cos theta, r sin theta).  Three normals per block: the pair from
  * (w0,w1) and the cosine member of the pair from (w2,w3).
+ *
+ * Per-step streams come in step pairs (2k, 2k+1), three blocks per bead or
+ * slot index and pair, all with counter step word k:
+ *   NOISE(i, k)  = x: Box-Muller pairs (x0,x1) -> (a0, a1), (x2,x3) -> (a2, a3);
+ *   NOISE2(i, k) = y: Box-Muller pair (y0,y1) -> (a4, a5); y2, y3 are the hop
+ *                  and reconstruction words of slot i at step 2k;
+ *   SLOT(j, k)   = z: z0, z1 are the hop and reconstruction words of slot j at
+ *                  step 2k+1 (z2, z3 unused).
+ * The bead noise is (a0, a1, a2) at step 2k and (a3, a4, a5) at step 2k+1.
+ * Six normals and four uniforms per pair take 1.5 blocks per step.
  */
 #include <math.h>
 #include <omp.h>
@@ -71,7 +81,8 @@ enum {
     P_INIT_ANCHOR = 4,
     P_NOISE = 5,
     P_SLOT = 6,
-    P_ANCHOR = 7
+    P_ANCHOR = 7,
+    P_NOISE2 = 8
 };
 
 void ssp_oracle_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
@@ -135,6 +146,55 @@ void ssp_oracle_normals3(uint64_t seed, int purpose, int index, int64_t chain, i
 void ssp_oracle_block(uint64_t seed, int purpose, int index, int64_t chain, int64_t step, uint32_t w[4])
 {
     draw(seed, purpose, index, chain, step, w);
+}
+
+/* The Box-Muller pair (r cos t, r sin t) of two words. */
+static void box_muller(uint32_t wa, uint32_t wb, double* c, double* s)
+{
+    double r = sqrt(-2.0 * log(ssp_oracle_u01(wa)));
+    double t = 2.0 * M_PI * ssp_oracle_u01(wb);
+    *c = r * cos(t);
+    *s = r * sin(t);
+}
+
+/* Noise normals of bead i of chain c at step `step` (step-pair layout above). */
+void ssp_oracle_step_noise(uint64_t seed, int i, int64_t c, int64_t step, double g[3])
+{
+    const int64_t k = step >> 1;
+    uint32_t x[4];
+    double a0, a1, a2, a3;
+    draw(seed, P_NOISE, i, c, k, x);
+    box_muller(x[0], x[1], &a0, &a1);
+    box_muller(x[2], x[3], &a2, &a3);
+    if ((step & 1) == 0) {
+        g[0] = a0;
+        g[1] = a1;
+        g[2] = a2;
+    } else {
+        uint32_t y[4];
+        double a4, a5;
+        draw(seed, P_NOISE2, i, c, k, y);
+        box_muller(y[0], y[1], &a4, &a5);
+        g[0] = a3;
+        g[1] = a4;
+        g[2] = a5;
+    }
+}
+
+/* Hop word w[0] and reconstruction word w[1] of slot j of chain c at step
+ * `step` (step-pair layout above). */
+void ssp_oracle_slot_words(uint64_t seed, int j, int64_t c, int64_t step, uint32_t w[2])
+{
+    uint32_t b[4];
+    if ((step & 1) == 0) {
+        draw(seed, P_NOISE2, j, c, step >> 1, b);
+        w[0] = b[2];
+        w[1] = b[3];
+    } else {
+        draw(seed, P_SLOT, j, c, step >> 1, b);
+        w[0] = b[0];
+        w[1] = b[1];
+    }
 }
 
 /* ---- Initial equilibrium state (Sec. 3.1, sampling procedure) ------------ */
@@ -265,7 +325,7 @@ static void move_chain(int n, int64_t c, const double* kap, double dt, double ns
     for (int i = 0; i < 3 * n; ++i) ro[i] = r[i];
     for (int i = 0; i < n; ++i) {
         double g[3];
-        ssp_oracle_normals3(seed, P_NOISE, i, c, step, g);
+        ssp_oracle_step_noise(seed, i, c, step, g);
         for (int d = 0; d < 3; ++d) {
             double flow = kap[3 * d + 0] * ro[3 * i + 0] + kap[3 * d + 1] * ro[3 * i + 1] + kap[3 * d + 2] * ro[3 * i + 2];
             r[3 * i + d] = ro[3 * i + d] + dt * (F[3 * i + d] + flow) + sq2dt * g[d];
@@ -305,7 +365,7 @@ static void step_chain(int n, int64_t c, const double* kap, double dt, double n0
         int i = s[j];
         double pp = ssp_oracle_hop_prob(n, r, a + 3 * j, i, +1, dt, ns, zeta_s);
         double pm = ssp_oracle_hop_prob(n, r, a + 3 * j, i, -1, dt, ns, zeta_s);
-        draw(seed, P_SLOT, j, c, step, w);
+        ssp_oracle_slot_words(seed, j, c, step, w);
         double u = ssp_oracle_u01(w[0]);
         if (u < pp) {
             s_after[j] = i + 1;
@@ -334,7 +394,7 @@ static void step_chain(int n, int64_t c, const double* kap, double dt, double n0
         if (p > 0.5) p = 0.5;
     }
     for (int j = 0; j < n; ++j) {
-        draw(seed, P_SLOT, j, c, step, w);
+        ssp_oracle_slot_words(seed, j, c, step, w);
         double u = ssp_oracle_u01(w[1]);
         if (s[j] >= 0) {
             int ends = (s[j] == 0) + (s[j] == n - 1);

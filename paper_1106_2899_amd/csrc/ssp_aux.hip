@@ -417,10 +417,22 @@ __global__ void k_rng_normals(uint32_t k0, uint32_t k1, uint32_t gid, int64_t st
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const v3<T> g = normals3<T>(draw(kNoise, (uint32_t)(bead + t), gid, step, k0, k1));
-    out[3 * t] = (double)g.x;
-    out[3 * t + 1] = (double)g.y;
-    out[3 * t + 2] = (double)g.z;
+    // the step-pair layout of the step kernel: NOISE pairs give (c, s, c) at
+    // the even step 2k; the odd step takes the last sine and the NOISE2 pair
+    const uint32_t idx = (uint32_t)(bead + t);
+    const T c = normal_scale<T>(1.0);
+    const uint4 x = draw(kNoise, idx, gid, step >> 1, k0, k1);
+    T g[6];
+    box_muller(x.x, x.y, c, g[0], g[1]);
+    box_muller(x.z, x.w, c, g[2], g[3]);
+    if (step & 1) {
+        const uint4 y = draw(kNoise2, idx, gid, step >> 1, k0, k1);
+        box_muller(y.x, y.y, c, g[4], g[5]);
+    }
+    const int o = (step & 1) ? 3 : 0;
+    out[3 * t] = (double)g[o];
+    out[3 * t + 1] = (double)g[o + 1];
+    out[3 * t + 2] = (double)g[o + 2];
 }
 
 }  // namespace

@@ -64,46 +64,96 @@ template <typename T> __device__ __forceinline__ T dot(v3<T> a, v3<T> b) { retur
 template <typename T> __device__ __forceinline__ v3<T> zero3() { return {T(0), T(0), T(0)}; }
 template <typename T> __device__ __forceinline__ v3<T> sel(bool c, v3<T> a, v3<T> b) { return c ? a : b; }
 
-// Box-Muller normals from four words: (r1 cos t1, r1 sin t1, r2 cos t2),
-// r = sqrt(-2 ln u_a), t = 2 pi u_b.
-__device__ __forceinline__ v3<float> normals3_f32(uint4 w)
+// Box-Muller normals from four words, scaled by sigma: sigma (r1 cos t1,
+// r1 sin t1, r2 cos t2), r = sqrt(-2 ln u_a), t = 2 pi u_b.  The scale enters
+// under the root: c = -2 sigma^2 (FP64, natural log) or -2 ln2 sigma^2 (FP32,
+// base-2 log).
+__device__ __forceinline__ v3<float> normals3_f32_scaled(uint4 w, float c)
 {
     const float u0 = u01<float>(w.x), u1 = u01<float>(w.y), u2 = u01<float>(w.z), u3 = u01<float>(w.w);
-    // -2 ln u = -2 ln2 log2 u; the hardware sine/cosine take revolutions.
-    const float r1 = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u0));
-    const float r2 = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u2));
+    // the hardware sine/cosine take revolutions
+    const float r1 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u0));
+    const float r2 = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u2));
     return {r1 * __builtin_amdgcn_cosf(u1), r1 * __builtin_amdgcn_sinf(u1), r2 * __builtin_amdgcn_cosf(u3)};
 }
-
-__device__ __forceinline__ v3<double> normals3_f64(uint4 w)
+__device__ __forceinline__ v3<double> normals3_f64_scaled(uint4 w, double c)
 {
     const double u0 = u01<double>(w.x), u1 = u01<double>(w.y), u2 = u01<double>(w.z), u3 = u01<double>(w.w);
-    const double r1 = sqrt(-2.0 * log(u0));
-    const double r2 = sqrt(-2.0 * log(u2));
+    const double r1 = sqrt(c * log(u0));
+    const double r2 = sqrt(c * log(u2));
     const double t1 = 2.0 * M_PI * u1;
     const double t2 = 2.0 * M_PI * u3;
     double s1, c1;
     sincos(t1, &s1, &c1);
     return {r1 * c1, r1 * s1, r2 * cos(t2)};
 }
+__device__ __forceinline__ v3<float> normals3_f32(uint4 w) { return normals3_f32_scaled(w, -1.38629436111989061883f); }
+__device__ __forceinline__ v3<double> normals3_f64(uint4 w) { return normals3_f64_scaled(w, -2.0); }
+
+// One Box-Muller pair scaled by sigma, (r cos t, r sin t) with
+// r = sigma sqrt(-2 ln u_a), t = 2 pi u_b; c as for normals3_*_scaled.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float c, float& cs, float& sn)
+{
+    const float r = __builtin_amdgcn_sqrtf(c * __builtin_amdgcn_logf(u01<float>(wa)));
+    const float t = u01<float>(wb);  // revolutions
+    cs = r * __builtin_amdgcn_cosf(t);
+    sn = r * __builtin_amdgcn_sinf(t);
+}
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double c, double& cs, double& sn)
+{
+    const double r = sqrt(c * log(u01<double>(wa)));
+    double s, co;
+    sincos(2.0 * M_PI * u01<double>(wb), &s, &co);
+    cs = r * co;
+    sn = r * s;
+}
+
+// The root constant c of normals3_*_scaled for standard deviation sigma.
+template <typename T> __device__ __forceinline__ T normal_scale(double sigma);
+template <> __device__ __forceinline__ float normal_scale<float>(double sigma) { return (float)(-2.0 * M_LN2 * sigma * sigma); }
+template <> __device__ __forceinline__ double normal_scale<double>(double sigma) { return -2.0 * sigma * sigma; }
+
+template <typename T> __device__ __forceinline__ v3<T> normals3_scaled(uint4 w, T c);
+template <> __device__ __forceinline__ v3<float> normals3_scaled<float>(uint4 w, float c) { return normals3_f32_scaled(w, c); }
+template <> __device__ __forceinline__ v3<double> normals3_scaled<double>(uint4 w, double c) { return normals3_f64_scaled(w, c); }
 
 template <typename T> __device__ __forceinline__ v3<T> normals3(uint4 w);
 template <> __device__ __forceinline__ v3<float> normals3<float>(uint4 w) { return normals3_f32(w); }
 template <> __device__ __forceinline__ v3<double> normals3<double>(uint4 w) { return normals3_f64(w); }
 
-// 1 - tanh(x) = 2 / (1 + e^{2x}), written to stay accurate when tanh -> 1.
-__device__ __forceinline__ float one_minus_tanh(float x)
+// Glauber hop probability min{h [1 - tanh(q y)], 1/2}, written as
+// min{2h / (1 + e^{2 q y}), 1/2}, which stays accurate when tanh -> 1.  The
+// caller passes h2 = 2h and e2q = 2q (FP64) or 2q log2(e) (FP32, base-2 exp).
+__device__ __forceinline__ float glauber(float y, float e2q, float h2)
 {
-    const float e = __builtin_amdgcn_exp2f(2.88539008177792681472f * x);  // e^{2x}
-    return 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+    return fminf(h2 * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(e2q * y)), 0.5f);
 }
-__device__ __forceinline__ double one_minus_tanh(double x) { return 2.0 / (1.0 + exp(2.0 * x)); }
+__device__ __forceinline__ double glauber(double y, double e2q, double h2) { return fmin(h2 / (1.0 + exp(e2q * y)), 0.5); }
+
+template <typename T> __device__ __forceinline__ T glauber_exp_scale(double q);
+template <> __device__ __forceinline__ float glauber_exp_scale<float>(double q) { return (float)(2.0 * q * M_LOG2E); }
+template <> __device__ __forceinline__ double glauber_exp_scale<double>(double q) { return 2.0 * q; }
+
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T> __device__ __forceinline__ v3<T> fma3(T s, v3<T> a, v3<T> b)
+{
+    return {fmat(s, a.x, b.x), fmat(s, a.y, b.y), fmat(s, a.z, b.z)};
+}
+// b + M r for a row-major 3x3 M, as fused multiply-adds.
+template <typename T> __device__ __forceinline__ v3<T> fma_mat3(const T* m, v3<T> r, v3<T> b)
+{
+    return {fmat(m[0], r.x, fmat(m[1], r.y, fmat(m[2], r.z, b.x))),
+            fmat(m[3], r.x, fmat(m[4], r.y, fmat(m[5], r.z, b.y))),
+            fmat(m[6], r.x, fmat(m[7], r.y, fmat(m[8], r.z, b.z)))};
+}
 
 // Neighbour exchange across the whole wavefront with DPP: lane i receives
 // lane i+1 (from_next, wave_shl:1) or lane i-1 (from_prev, wave_shr:1); the
-// lane without a source receives 0.
-__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+// lane without a source receives 0 (bound_ctrl), which also lets the compiler
+// fold the shift into the instruction that consumes it.
+__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 __device__ __forceinline__ float from_next(float v) { return __builtin_bit_cast(float, dpp_next_i(__builtin_bit_cast(int, v))); }
 __device__ __forceinline__ float from_prev(float v) { return __builtin_bit_cast(float, dpp_prev_i(__builtin_bit_cast(int, v))); }
 __device__ __forceinline__ double from_next(double v)

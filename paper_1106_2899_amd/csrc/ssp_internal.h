@@ -28,7 +28,8 @@ enum Purpose : uint32_t {
     kInitAnchor = 4,
     kNoise = 5,
     kSlot = 6,
-    kAnchor = 7
+    kAnchor = 7,
+    kNoise2 = 8
 };
 
 struct ChainTables {

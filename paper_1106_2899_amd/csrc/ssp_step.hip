@@ -133,6 +133,10 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     constexpr int kCap = W * B;  // bead capacity of a segment
 
     __shared__ WaveLds<T, B> lds[kWavesPerGroup];
+    // creation thresholds for p_K and 2 p_K, K = 0..kMaxBeads, read every step
+    __shared__ uint32_t thr[2 * (kMaxBeads + 1)];
+    for (int q = threadIdx.x; q < 2 * (kMaxBeads + 1); q += kGroupThreads) thr[q] = a.thr[q];
+    __syncthreads();
 
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wv = threadIdx.x / kWaveSize;
@@ -152,20 +156,23 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     Off4<T>* offs = lds[wv].off;
     const int lbase = seg * kCap;  // this segment's first entry in the LDS arrays
 
-    const T dt = T(a.ph.dt);
-    const T ks = T(3.0 / a.ph.ns);                   // slip-spring stiffness 3/N_s
-    const T sq2dt = T(sqrt(2.0 * a.ph.dt));
-    const T ch = T(a.ph.dt / a.ph.zeta_s);           // dt / zeta_s
-    const T qh = T(3.0 / (4.0 * a.ph.ns));           // 3/(4 N_s), Glauber argument scale
-    const T asd = T(sqrt(a.ph.ns / 3.0));            // anchor offset s.d.
+    // Step constants with dt folded in: the move is
+    //   R += sqrt(2 dt) w + 3 dt (b_right - b_left) - (3/N_s) dt sum_j d_j + dt kappa R.
+    const T cnoise = normal_scale<T>(sqrt(2.0 * a.ph.dt));  // Box-Muller root constant for s.d. sqrt(2 dt)
+    const T cbond = T(3.0 * a.ph.dt);
+    const T cspring = T(3.0 / a.ph.ns * a.ph.dt);
+    const T hop_h2 = T(2.0 * a.ph.dt / a.ph.zeta_s);                    // 2 dt / zeta_s
+    const T hop_e2q = glauber_exp_scale<T>(3.0 / (4.0 * a.ph.ns));     // Glauber argument scale 3/(4 N_s)
+    const T asd = T(sqrt(a.ph.ns / 3.0));                               // anchor offset s.d.
     const uint32_t k0 = a.ph.key0, k1 = a.ph.key1;
 
-    T kap[9];
+    T kdt[9];  // dt kappa of the chain's element
     bool has_flow = false;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
-        has_flow |= kap[q] != T(0);
+        const double kq = valid ? a.kappa[9 * elem + q] : 0.0;
+        kdt[q] = T(a.ph.dt * kq);
+        has_flow |= kq != 0.0;
     }
     const bool flow = wave_any(has_flow);
 
@@ -198,15 +205,17 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             const int i = li * B + b;
             const v3<T> h = (b + 1 < B) ? rh[b + 1 < B ? b + 1 : b] : nh;
             const v3<T> l = (b + 1 < B) ? rl[b + 1 < B ? b + 1 : b] : nl;
-            br[b] = (i < n - 1) ? ((h - rh[b]) + (l - rl[b])) : zero3<T>();
+            const v3<T> v = (h - rh[b]) + (l - rl[b]);  // computed everywhere, then selected
+            br[b] = sel(i < n - 1, v, zero3<T>());
         }
+        // The bond from the left needs no mask: the lane before the first lane
+        // of a segment holds the previous segment's last bead (or is lane 0 of
+        // the wave, which DPP fills with 0), and its right bond is zero since
+        // it lies at or past that chain's end; past the end of this chain
+        // the right bonds are zero as well.
         const v3<T> left = from_prev3(br[B - 1]);
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int i = li * B + b;
-            const v3<T> v = (b > 0) ? br[b > 0 ? b - 1 : 0] : left;
-            bl[b] = (i > 0 && i < n) ? v : zero3<T>();
-        }
+        for (int b = 0; b < B; ++b) bl[b] = (b > 0) ? br[b > 0 ? b - 1 : 0] : left;
 #pragma unroll
         for (int b = 0; b < B; ++b) rec_put(rec[lbase + li * B + b], rh[b], rl[b], br[b], bl[b]);
         wave_sync();
@@ -259,12 +268,39 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 
     const int64_t g0 = a.ctrl[kCtrlSteps];
     bool finite_ok = true;
+
+    // Random streams come in step pairs (2k, 2k+1), three Philox blocks per
+    // bead/slot index and pair (counter step word k):
+    //   NOISE  -> Box-Muller pairs (x0,x1), (x2,x3): noise (c, s, c) of step 2k
+    //             and the first normal of step 2k+1 (carried);
+    //   NOISE2 -> hop / reconstruction words y2, y3 of step 2k; y0, y1 (carried)
+    //             make the Box-Muller pair of the other two normals of 2k+1;
+    //   SLOT   -> hop / reconstruction words z0, z1 of step 2k+1.
+    // A launch that starts at an odd step rebuilds the carried values.
+    T carry_n[B];
+    uint32_t carry_w0[B], carry_w1[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        carry_n[b] = T(0);
+        carry_w0[b] = carry_w1[b] = 0u;
+        if (g0 & 1) {
+            const uint32_t i = (uint32_t)(li * B + b);
+            const uint4 x = draw(kNoise, i, gid, g0 >> 1, k0, k1);
+            T c;
+            box_muller(x.z, x.w, cnoise, c, carry_n[b]);
+            const uint4 y = draw(kNoise2, i, gid, g0 >> 1, k0, k1);
+            carry_w0[b] = y.x;
+            carry_w1[b] = y.y;
+        }
+    }
     // sampling phase: step g is sampled when (g + 1) % sample_every == 0
     int phase = a.sample_every > 0 ? (int)((g0 + 1) % a.sample_every) : 1;
     int64_t q_launch = 0;  // samples already written by this launch
 
     for (int step = 0; step < a.n_steps; ++step) {
         const int64_t g = g0 + step;
+        const bool even = (g & 1) == 0;  // wave-uniform
+        const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
 
         // ---- substep 1a: slip-spring force, sum of d_j over the springs of each
         // bead, delivered in increasing slot order (one spring per bead per round).
@@ -308,15 +344,19 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
-            const uint4 w = draw(kNoise, (uint32_t)i, gid, g, k0, k1);
-            const v3<T> gn = normals3<T>(w);
-            v3<T> F = T(3) * (br[b] - bl[b]) - ks * acc[b];
-            if (flow) {  // wave-uniform; F + 0 = F keeps chains without flow bit-identical
-                const v3<T> r = rh[b];
-                F = F + v3<T>{kap[0] * r.x + kap[1] * r.y + kap[2] * r.z, kap[3] * r.x + kap[4] * r.y + kap[5] * r.z,
-                              kap[6] * r.x + kap[7] * r.y + kap[8] * r.z};
+            v3<T> inc;  // sqrt(2 dt) w
+            if (even) {
+                const uint4 x = draw(kNoise, (uint32_t)i, gid, kp, k0, k1);
+                box_muller(x.x, x.y, cnoise, inc.x, inc.y);
+                box_muller(x.z, x.w, cnoise, inc.z, carry_n[b]);
+            } else {
+                inc.x = carry_n[b];
+                box_muller(carry_w0[b], carry_w1[b], cnoise, inc.y, inc.z);
             }
-            const v3<T> inc = dt * F + sq2dt * gn;
+            inc = fma3(cbond, br[b] - bl[b], inc);
+            inc = fma3(-cspring, acc[b], inc);
+            // wave-uniform branch; fma(0, r, x) = x keeps chains without flow bit-identical
+            if (flow) inc = fma_mat3(kdt, rh[b], inc);
             if (i < n) {
                 if constexpr (kComp)
                     cadd3(rh[b], rl[b], inc);
@@ -328,9 +368,8 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const v3<T> A = ah[b];
-                const v3<T> inc = dt * v3<T>{kap[0] * A.x + kap[1] * A.y + kap[2] * A.z,
-                                             kap[3] * A.x + kap[4] * A.y + kap[5] * A.z,
-                                             kap[6] * A.x + kap[7] * A.y + kap[8] * A.z};
+                const v3<T> inc = {kdt[0] * A.x + kdt[1] * A.y + kdt[2] * A.z, kdt[3] * A.x + kdt[4] * A.y + kdt[5] * A.z,
+                                   kdt[6] * A.x + kdt[7] * A.y + kdt[8] * A.z};
                 if (s[b] >= 0) {
                     if constexpr (kComp)
                         cadd3(ah[b], al[b], inc);
@@ -342,11 +381,22 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         bonds_and_records();
 
         // ---- substep 2: hops from the post-move positions.
-        uint4 ws[B];
+        uint32_t wrec[B];  // reconstruction words
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = li * B + b;
-            ws[b] = draw(kSlot, (uint32_t)j, gid, g, k0, k1);
+            uint32_t whop;
+            if (even) {
+                const uint4 y = draw(kNoise2, (uint32_t)j, gid, kp, k0, k1);
+                whop = y.z;
+                wrec[b] = y.w;
+                carry_w0[b] = y.x;
+                carry_w1[b] = y.y;
+            } else {
+                const uint4 z = draw(kSlot, (uint32_t)j, gid, kp, k0, k1);
+                whop = z.x;
+                wrec[b] = z.y;
+            }
             const int t = s[b] > 0 ? s[b] : 0;
             const BeadRec<T> r = rec[lbase + t];
             const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
@@ -357,9 +407,9 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             // (R_{S+-1} - A)^2 - (R_S - A)^2 = b (b + 2 d) with b = R_{S+-1} - R_S
             const T up = dot(bp, bp + T(2) * dd);
             const T dn = dot(bm, bm + T(2) * dd);
-            const T pp = (t < n - 1) ? fmin(ch * one_minus_tanh(qh * up), T(0.5)) : T(0);
-            const T pm = (t > 0) ? fmin(ch * one_minus_tanh(qh * dn), T(0.5)) : T(0);
-            const T u = u01<T>(ws[b].x);
+            const T pp = (t < n - 1) ? glauber(up, hop_e2q, hop_h2) : T(0);
+            const T pm = (t > 0) ? glauber(dn, hop_e2q, hop_h2) : T(0);
+            const T u = u01<T>(whop);
             if (s[b] >= 0) {
                 if (u < pp)
                     s[b] = t + 1;
@@ -373,14 +423,14 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 #pragma unroll
         for (int b = 0; b < B; ++b) z += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
         const int K = n - z;
-        const uint32_t t1 = a.thr[K < 0 ? 0 : K];
-        const uint32_t t2 = a.thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
+        const uint32_t t1 = thr[K < 0 ? 0 : K];
+        const uint32_t t2 = thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
         int create_at[B];
         bool any_create = false;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = li * B + b;
-            const uint32_t uw = ws[b].y >> 9;
+            const uint32_t uw = wrec[b] >> 9;
             create_at[b] = -1;
             if (j < n) {
                 if (s[b] >= 0) {

@@ -57,11 +57,12 @@ def _rel_err(g, o):
 
 # ----------------------------------------------------------------- RNG -----
 
+@pytest.mark.parametrize("step", [(1 << 33) + 4, (1 << 33) + 5])  # both members of a step pair
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_rng_normals_match_oracle(precision):
+def test_rng_normals_match_oracle(precision, step):
     e = _ens(8, 4, precision=precision, seed=12345)
-    got = e.rng_normals(chain_id=77, step=(1 << 33) + 5, bead=3, count=4096).cpu().numpy()
-    want = np.array([oracle.normals3(12345, oracle.P_NOISE, 3 + i, 77, (1 << 33) + 5) for i in range(4096)])
+    got = e.rng_normals(chain_id=77, step=step, bead=3, count=4096).cpu().numpy()
+    want = np.array([oracle.step_noise(12345, 3 + i, 77, step) for i in range(4096)])
     err = np.abs(got - want)
     if precision == "fp64":
         assert err.max() < 1e-13
