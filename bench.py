@@ -32,23 +32,29 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: full-rate
 
 
 def algorithmic_valu_slots(sample_every: int = SAMPLE_EVERY, n0: float = 4.0) -> float:
-    """VALU issue slots per bead-step that the method needs, weighting each
-    operation by its issue cost measured on gfx950 with a throughput probe
-    (full rate = 1, which includes the 32x32->64 integer multiply and the
-    three-input bitop; FP32 transcendentals log/exp/sin/cos/sqrt/rcp = 2;
-    FP64 FMA = 1):
-      two Philox4x32-10 blocks (bead noise, slot uniforms): 10 rounds x
-        (2 products + 2 three-input xors) = 40 each             ->  80
-      Box-Muller, 3 normals: 4 uniforms x 3, 2 log, 2 sqrt,
-        3 sin/cos (x2 each), 5 multiplies                        ->  31
-      forces, flow, Euler move: bonds 3, bond force 6, spring 3,
-        kappa.R 9, increment 9, position update 3                ->  33
-      hop per occupied slot (fraction 1/N_0): offset 3, two energy
-        differences 12, two probabilities 2 x 8, decision 3      ->  34 / N_0
-      reconstruction threshold tests                             ->   2
-      stress and virtual stress products (FP64), per sample      -> 7.5 / n_s
+    """VALU lane-issue slots per bead-step that the method needs on this
+    workload (kappa = 0), each operation weighted by its issue cost measured
+    on gfx950 with a throughput probe (full rate = 1, which includes the
+    32x32->64 integer multiply, the three-input bitop and FP64 FMA; FP32
+    transcendentals log/exp/sin/cos/sqrt/rcp = 2), in the arithmetic the path
+    requires (compensated FP32 positions) and with the random stream at its
+    minimum of five words per bead-step:
+      random words: 1.5 Box-Muller pairs (3 words) + hop + reconstruction
+        = 1.25 Philox4x32-10 blocks x 10 rounds x (2 products + 2 xors)  ->  50
+      Box-Muller, 1.5 pairs x (2 uniforms x 2, log 2, mul, sqrt 2,
+        sin 2, cos 2, 2 mul)                                           ->  22.5
+      bonds from compensated positions, 3 x 3                          ->   9
+      move: bond-force difference 3, two FMAs per component 6,
+        compensated position update 12                                 ->  21
+      spring-force gather, 3 adds per spring                           ->   3 / N_0
+      hop per occupied slot: post-move offset 3, two energy
+        differences 12, two probabilities 2 x 8, decision 5            ->  36 / N_0
+      reconstruction word test                                         ->   2
+      anchor offsets for the next step (compensated), per spring      ->   9 / N_0
+      stress and virtual stress (FP64), per sample: per bead 3 cvt
+        + 6 FMA, per spring the same                                   ->  (9 + 9 / N_0) / n_s
     """
-    return 80.0 + 31.0 + 33.0 + 34.0 / n0 + 2.0 + 7.5 / sample_every
+    return 50.0 + 22.5 + 9.0 + 21.0 + 3.0 / n0 + 36.0 / n0 + 2.0 + 9.0 / n0 + (9.0 + 9.0 / n0) / sample_every
 
 
 def _sha(path):

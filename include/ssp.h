@@ -82,13 +82,19 @@ typedef struct ssp_config {
     int32_t corr_batches;           /* chain groups for batch-means errors, 1..64 */
     int64_t series_capacity;        /* samples kept per element (0 disables the element series) */
     int32_t use_graph;              /* 1: ssp_step replays a captured hipGraph; 0: plain launches */
-    int32_t reserved[7];
+    int32_t construct_rule;         /* slip-spring construction attempts per step (Sec. 3.2):
+                                       0 = K = C - Z (every empty slot attempts once, the GPU rule),
+                                       1 = K = 1 (one attempt, by the lowest empty slot: the CPU rule) */
+    int32_t corr_virtual;           /* 1: the correlator also accumulates <sigma^v(t) [sigma + sigma^v](0)>
+                                       (ssp_read_correlator_virtual); 0: off */
+    int32_t reserved[5];
 } ssp_config;
 
 /* Fills *cfg with the paper's standard parameters (Sec. 4.1): N_0 = 4,
  * N_s = 0.5, zeta_s = 0.1, dt = 0.01, plus n_chains = 1, n_elements = 1,
  * n_beads = 8, precision FP32, sample_every = 1, seed = 1, corr_levels 16,
- * corr_lags 16, corr_batches 16, series_capacity 0, use_graph 1. */
+ * corr_lags 16, corr_batches 16, series_capacity 0, use_graph 1,
+ * construct_rule 0, corr_virtual 0. */
 int ssp_config_init(ssp_config* cfg);
 
 /* Bytes the caller must allocate on the device for the state and the work
@@ -157,6 +163,37 @@ int ssp_read_element_series(ssp_handle* h, double* out_dev, int64_t* n_samples_h
  * sums are Neumaier-compensated.  Synchronises the stream. */
 int ssp_read_correlator(ssp_handle* h, double* G_dev, double* G_err_dev, double* tau_host, int64_t* counts_host,
                         ssp_stream stream);
+
+/* The virtual-stress channel of the correlator (config corr_virtual = 1):
+ * Gv(t) = <sigma^v_ab(t) [sigma_ab + sigma^v_ab](t0)> per chain in kBT units,
+ * averaged over ab in {xy, yz, zx}, on the same multiple-tau grid, counts and
+ * batch-means errors as ssp_read_correlator.  Gv(t) / G(t) is the relative
+ * contribution of the virtual stress to the shear relaxation modulus of
+ * Sec. 4.1 (its numerator <sigma^v(t) sigma> + <sigma^v(t) sigma^v> over the
+ * denominator <sigma(t) sigma> + <sigma(t) sigma^v>).  Gv_dev, Gv_err_dev:
+ * [corr_levels][16] FP64 (device).  Synchronises the stream.  SSP_ESTATE when
+ * the channel is off. */
+int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_dev, ssp_stream stream);
+
+/* Linear viscoelasticity from the relaxation modulus (the relations of
+ * Sec. 4.1): G'(w) = w int G(t) sin(w t) dt, G''(w) = w int G(t) cos(w t) dt,
+ * |eta*(w)| = |G' + i G''| / w, eta_0 = int G(t) dt, and the longest
+ * relaxation time from 1/tau_d = -lim ln G(t) / t.
+ * G_dev: [corr_levels][16] FP64 device array as written by ssp_read_correlator
+ * (or any modulus on that grid), read on the grid of the handle's current
+ * sample count: level 0 lags 0..15, level l >= 1 lags 8..15, lag times
+ * k 2^l sample_every dt, lags with data only.  The integrals take G piecewise
+ * linear between grid points (the trapezoidal rule's model of G) and
+ * integrate that exactly against sin and cos, up to the last point with data;
+ * eta_0 is the trapezoidal sum.  tau_d = -1 / (least-squares slope of ln G
+ * against t over the grid points with t_lo <= t <= t_hi and G > 0); NaN with
+ * fewer than two such points or a slope that is not negative.
+ * omega_dev: [n_omega] angular frequencies > 0 (device); moduli_dev:
+ * [n_omega][3] FP64 G', G'', |eta*| (device); scalars_dev: [2] FP64 eta_0,
+ * tau_d (device).  Asynchronous.  SSP_ESTATE without a correlator;
+ * SSP_EINVAL for missing buffers, n_omega < 0 or t_lo > t_hi. */
+int ssp_linear_viscoelasticity(ssp_handle* h, const double* G_dev, const double* omega_dev, int32_t n_omega,
+                               double t_lo, double t_hi, double* moduli_dev, double* scalars_dev, ssp_stream stream);
 
 /* Clears the correlator and the element series; the next sample is t = 0. */
 int ssp_reset_observables(ssp_handle* h, ssp_stream stream);

@@ -61,9 +61,10 @@ def lib():
         L.ssp_oracle_init.argtypes = [ctypes.c_int, i32p, i64p, i64p, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, f64p, f64p, i32p]
         L.ssp_oracle_stress.argtypes = [ctypes.c_int, i32p, i64p, ctypes.c_double, f64p, f64p, i32p, f64p]
         L.ssp_oracle_step.argtypes = [ctypes.c_int, i32p, i64p, i64p, f64p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, f64p, f64p, i32p, u8p, f64p]
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, f64p, f64p, i32p, u8p, f64p]
         L.ssp_oracle_run.argtypes = [ctypes.c_int, i32p, i64p, i64p, f64p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, f64p, f64p, i32p, f64p]
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                     f64p, f64p, i32p, f64p]
         L.ssp_oracle_run.restype = ctypes.c_int64
         L.ssp_oracle_multitau.argtypes = [ctypes.c_int64, f64p, f64p, ctypes.c_int, ctypes.c_int, f64p, i64p]
         L.ssp_oracle_threads.argtypes = []
@@ -145,7 +146,9 @@ def multitau(x, y, levels=16, lags=16):
 class Ensemble:
     """Host-side FP64 state of an ensemble of chains (slot capacity C = N)."""
 
-    def __init__(self, n_beads, chain_ids=None, n0=4.0, ns=0.5, zeta_s=0.1, dt=0.01, seed=1):
+    def __init__(self, n_beads, chain_ids=None, n0=4.0, ns=0.5, zeta_s=0.1, dt=0.01, seed=1, construct_rule=0):
+        """construct_rule: 0 = K = C - Z construction attempts (the GPU rule of
+        Sec. 3.2), 1 = K = 1 (the CPU rule of Sec. 3.2)."""
         self.N = np.ascontiguousarray(n_beads, dtype=np.int32)
         self.M = int(self.N.shape[0])
         if np.any(self.N < 2):
@@ -156,6 +159,7 @@ class Ensemble:
         self.total = int(self.N.sum())
         self.chain_ids = np.ascontiguousarray(np.arange(self.M) if chain_ids is None else chain_ids, dtype=np.int64)
         self.n0, self.ns, self.zeta_s, self.dt, self.seed = float(n0), float(ns), float(zeta_s), float(dt), int(seed)
+        self.construct_rule = int(construct_rule)
         self.R = np.zeros((self.total, 3))
         self.A = np.zeros((self.total, 3))
         self.S = np.full(self.total, -1, dtype=np.int32)
@@ -184,7 +188,7 @@ class Ensemble:
         ev = np.zeros(self.total, dtype=np.uint8) if want_events else None
         mg = np.zeros(self.total) if want_events else None
         lib().ssp_oracle_step(self.M, Np, op, cp, _p(k, ctypes.c_double), self.dt, self.n0, self.ns, self.zeta_s,
-                              self.seed, self.step_index, _p(self.R, ctypes.c_double), _p(self.A, ctypes.c_double),
+                              self.construct_rule, self.seed, self.step_index, _p(self.R, ctypes.c_double), _p(self.A, ctypes.c_double),
                               _p(self.S, ctypes.c_int32),
                               _p(ev, ctypes.c_uint8) if want_events else None,
                               _p(mg, ctypes.c_double) if want_events else None)
@@ -199,7 +203,7 @@ class Ensemble:
         T = sum(1 for t in range(self.step_index, self.step_index + n_steps) if (t + 1) % sample_every == 0)
         samples = np.zeros((T, self.M, 12)) if keep_samples else None
         lib().ssp_oracle_run(self.M, Np, op, cp, _p(k, ctypes.c_double), self.dt, self.n0, self.ns, self.zeta_s,
-                             self.seed, self.step_index, n_steps, sample_every, _p(self.R, ctypes.c_double),
+                             self.construct_rule, self.seed, self.step_index, n_steps, sample_every, _p(self.R, ctypes.c_double),
                              _p(self.A, ctypes.c_double), _p(self.S, ctypes.c_int32),
                              _p(samples, ctypes.c_double) if keep_samples else None)
         self.step_index += n_steps

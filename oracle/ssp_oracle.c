@@ -31,7 +31,9 @@
  *    p = min(dt/(zeta_s N0 K), 1/2) at bead 0 and p at bead N-1 (one
  *    uniform: [0,p) -> bead 0, [p,2p) -> bead N-1).  Occupied slots sitting
  *    on an end are destroyed with min(dt/zeta_s (delta_{S,0}+delta_{S,N-1}), 1).
- *    A spring created in this step is not tested for destruction.
+ *    A spring created in this step is not tested for destruction.  The CPU
+ *    rule K = 1 of Sec. 3.2 is a variant: only the lowest empty slot attempts,
+ *    with p = min(dt/(zeta_s N0), 1/2).
  *  - Virtual stress sums over all Z springs (Appendix B form).
  *  - Initial Z is drawn from Poisson(N/N0) truncated to 0..C.
  *
@@ -342,7 +344,7 @@ static void move_chain(int n, int64_t c, const double* kap, double dt, double ns
 }
 
 static void step_chain(int n, int64_t c, const double* kap, double dt, double n0, double ns, double zeta_s,
-                       uint64_t seed, int64_t step, double* r, double* a, int32_t* s, uint8_t* ev,
+                       int rule, uint64_t seed, int64_t step, double* r, double* a, int32_t* s, uint8_t* ev,
                        double* margin, double* F, double* ro)
 {
     const double anchor_sd = sqrt(ns / 3.0);
@@ -384,10 +386,17 @@ static void step_chain(int n, int64_t c, const double* kap, double dt, double n0
     for (int j = 0; j < n; ++j) s[j] = s_after[j];
     free(s_after);
 
-    /* Substep 3: reconstruction at the chain ends from the post-hop state. */
-    int z = 0;
-    for (int j = 0; j < n; ++j) z += (s[j] >= 0);
-    int kattempt = n - z;
+    /* Substep 3: reconstruction at the chain ends from the post-hop state.
+     * Construction is attempted K times (Sec. 3.1 substep 3).  Rule 0, the GPU
+     * rule of Sec. 3.2: K = C - Z, every empty slot attempts once.  Rule 1, the
+     * CPU rule of Sec. 3.2: K = 1, a single attempt, made by the lowest empty
+     * slot (none when all C slots are occupied). */
+    int z = 0, first_empty = -1;
+    for (int j = 0; j < n; ++j) {
+        z += (s[j] >= 0);
+        if (s[j] < 0 && first_empty < 0) first_empty = j;
+    }
+    int kattempt = rule == 1 ? (z < n ? 1 : 0) : n - z;
     double p = 0.0;
     if (kattempt > 0) {
         p = dt / (zeta_s * n0 * (double)kattempt);
@@ -410,7 +419,7 @@ static void step_chain(int n, int64_t c, const double* kap, double dt, double n0
                 double m = fabs(u - pd);
                 if (m < margin[j]) margin[j] = m;
             }
-        } else {
+        } else if (rule == 0 || j == first_empty) {
             int at = -1;
             if (u < p) {
                 at = 0;
@@ -485,7 +494,7 @@ void ssp_oracle_stress(int n_chains, const int32_t* N, const int64_t* off, doubl
 
 /* One step for all chains.  events/margin may be NULL. */
 void ssp_oracle_step(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
-                     const double* kappa, double dt, double n0, double ns, double zeta_s, uint64_t seed,
+                     const double* kappa, double dt, double n0, double ns, double zeta_s, int rule, uint64_t seed,
                      int64_t step, double* R, double* A, int32_t* S, uint8_t* events, double* margin)
 {
 #pragma omp parallel for schedule(dynamic, 8)
@@ -494,8 +503,8 @@ void ssp_oracle_step(int n_chains, const int32_t* N, const int64_t* off, const i
         int64_t o = off[k];
         double* F = (double*)malloc(sizeof(double) * 3 * (size_t)n);
         double* ro = (double*)malloc(sizeof(double) * 3 * (size_t)n);
-        step_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, n0, ns, zeta_s, seed, step, R + 3 * o, A + 3 * o,
-                   S + o, events ? events + o : NULL, margin ? margin + o : NULL, F, ro);
+        step_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, n0, ns, zeta_s, rule, seed, step, R + 3 * o,
+                   A + 3 * o, S + o, events ? events + o : NULL, margin ? margin + o : NULL, F, ro);
         free(F);
         free(ro);
     }
@@ -506,7 +515,7 @@ void ssp_oracle_step(int n_chains, const int32_t* N, const int64_t* off, const i
  * sample_every.  samples: [n_samples][n_chains][12] (may be NULL).  Returns
  * the number of samples written. */
 int64_t ssp_oracle_run(int n_chains, const int32_t* N, const int64_t* off, const int64_t* chain_id,
-                       const double* kappa, double dt, double n0, double ns, double zeta_s, uint64_t seed,
+                       const double* kappa, double dt, double n0, double ns, double zeta_s, int rule, uint64_t seed,
                        int64_t step0, int64_t n_steps, int64_t sample_every, double* R, double* A, int32_t* S,
                        double* samples)
 {
@@ -521,8 +530,8 @@ int64_t ssp_oracle_run(int n_chains, const int32_t* N, const int64_t* off, const
         double* ro = (double*)malloc(sizeof(double) * 3 * (size_t)n);
         int64_t q = 0;
         for (int64_t t = step0; t < step0 + n_steps; ++t) {
-            step_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, n0, ns, zeta_s, seed, t, R + 3 * o, A + 3 * o,
-                       S + o, NULL, NULL, F, ro);
+            step_chain(n, chain_id[k], kappa + 9 * (int64_t)k, dt, n0, ns, zeta_s, rule, seed, t, R + 3 * o,
+                       A + 3 * o, S + o, NULL, NULL, F, ro);
             if ((t + 1) % sample_every == 0) {
                 if (samples) stress_chain(n, ns, R + 3 * o, A + 3 * o, S + o, samples + 12 * ((int64_t)n_chains * q + k));
                 ++q;

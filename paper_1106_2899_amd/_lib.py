@@ -32,6 +32,8 @@ EXPORTS = [
     "ssp_write_state",
     "ssp_read_element_series",
     "ssp_read_correlator",
+    "ssp_read_correlator_virtual",
+    "ssp_linear_viscoelasticity",
     "ssp_reset_observables",
     "ssp_step_count",
     "ssp_rng_normals",
@@ -67,7 +69,9 @@ class SspConfig(ctypes.Structure):
         ("corr_batches", ctypes.c_int32),
         ("series_capacity", ctypes.c_int64),
         ("use_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("construct_rule", ctypes.c_int32),
+        ("corr_virtual", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -102,6 +106,8 @@ def lib():
             "ssp_write_state": [vp, vp, vp, vp, vp],
             "ssp_read_element_series": [vp, vp, ctypes.POINTER(ctypes.c_int64), vp],
             "ssp_read_correlator": [vp, vp, vp, f64p, ctypes.POINTER(ctypes.c_int64), vp],
+            "ssp_read_correlator_virtual": [vp, vp, vp, vp],
+            "ssp_linear_viscoelasticity": [vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, vp, vp, vp],
             "ssp_reset_observables": [vp, vp],
             "ssp_step_count": [vp, ctypes.POINTER(ctypes.c_int64)],
             "ssp_rng_normals": [vp, i64, i64, i32, i32, vp, vp],

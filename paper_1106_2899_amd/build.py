@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libssp.so")
 
-SOURCES = ["ssp_step.hip", "ssp_aux.hip", "ssp_adjoint.hip", "ssp_api.cpp"]
+SOURCES = ["ssp_step.hip", "ssp_aux.hip", "ssp_adjoint.hip", "ssp_moduli.hip", "ssp_api.cpp"]
 HEADERS = ["ssp_device.h", "ssp_internal.h"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler

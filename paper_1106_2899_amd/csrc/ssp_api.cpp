@@ -50,8 +50,8 @@ bool mapping_supported(int W, int B)
 
 struct Layout {
     // work buffer offsets (bytes)
-    size_t ctrl, flags, off, n, elem, gid, tasks, elem_off, thr, samples, hist, acc, pend, batch, series, corr_out,
-        total;
+    size_t ctrl, flags, off, n, elem, gid, tasks, elem_off, thr, samples, hist, acc, pend, acc_v, pend_v, batch,
+        series, corr_out, total;
     // state buffer offsets
     size_t r0, r1, a0, a1, s, state_total;
     int64_t q_cap;
@@ -117,6 +117,14 @@ bool resolve(const ssp_config* c, Resolved& r, std::string& err)
     }
     if (k.max_steps_per_launch < 0) {
         err = "max_steps_per_launch must be >= 0";
+        return false;
+    }
+    if (k.construct_rule != 0 && k.construct_rule != 1) {
+        err = "construct_rule must be 0 (K = C - Z) or 1 (K = 1)";
+        return false;
+    }
+    if (k.corr_virtual != 0 && k.corr_virtual != 1) {
+        err = "corr_virtual must be 0 or 1";
         return false;
     }
     const int64_t M = k.n_chains;
@@ -197,6 +205,9 @@ Layout make_layout(const Resolved& r)
     L.hist = take(lv ? sizeof(double) * (size_t)lv * 3 * M * 16 : 0);
     L.acc = take(lv ? sizeof(double) * (size_t)lv * 3 * M * 16 : 0);
     L.pend = take(lv ? sizeof(double) * (size_t)3 * M * 16 * 2 : 0);
+    const bool cv = lv && k.corr_virtual;
+    L.acc_v = take(cv ? sizeof(double) * (size_t)lv * 3 * M * 16 : 0);
+    L.pend_v = take(cv ? sizeof(double) * (size_t)3 * M * 16 : 0);
     L.batch = take(lv ? sizeof(double) * (size_t)k.corr_batches * lv * 16 : 0);
     L.corr_out = take(lv ? sizeof(double) * (size_t)lv * 16 * 2 : 0);
     L.series = take(sizeof(double) * (size_t)k.n_elements * k.series_capacity * 6);
@@ -324,6 +335,7 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
             a.kappa = kappa;
             a.thr = reinterpret_cast<const uint32_t*>(h->work + h->lay.thr);
             a.thr_destroy = threshold(std::min(k.dt / k.zeta_s * 1.0, 1.0));
+            a.construct_rule = k.construct_rule;
             a.ph = h->phys();
             a.ctrl = h->ctrl();
             a.n_steps = m;
@@ -347,6 +359,10 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
             c.hist = reinterpret_cast<double*>(h->work + h->lay.hist);
             c.acc = reinterpret_cast<double*>(h->work + h->lay.acc);
             c.pend = reinterpret_cast<double*>(h->work + h->lay.pend);
+            if (k.corr_virtual) {
+                c.acc_v = reinterpret_cast<double*>(h->work + h->lay.acc_v);
+                c.pend_v = reinterpret_cast<double*>(h->work + h->lay.pend_v);
+            }
             c.n_chains = M;
             c.levels = k.corr_levels;
             c.n_steps = m;
@@ -401,6 +417,10 @@ int zero_observables(ssp_handle* h, hipStream_t s)
         HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.hist), (int64_t)k.corr_levels * 3 * M * 16, s));
         HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.acc), (int64_t)k.corr_levels * 3 * M * 16, s));
         HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.pend), 3 * M * 16 * 2, s));
+        if (k.corr_virtual) {
+            HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.acc_v), (int64_t)k.corr_levels * 3 * M * 16, s));
+            HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.pend_v), 3 * M * 16, s));
+        }
     }
     if (k.series_capacity > 0)
         HIPCHK(h, launch_zero(reinterpret_cast<double*>(h->work + h->lay.series),
@@ -434,6 +454,8 @@ int ssp_config_init(ssp_config* c)
     c->corr_batches = 16;
     c->series_capacity = 0;
     c->use_graph = 1;
+    c->construct_rule = 0;
+    c->corr_virtual = 0;
     return SSP_OK;
 }
 
@@ -669,6 +691,40 @@ int ssp_read_correlator(ssp_handle* h, double* G_dev, double* G_err_dev, double*
     return check_flags(h, s);
 }
 
+int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    const ssp_config& k = h->res.cfg;
+    if (k.corr_levels == 0 || !k.corr_virtual)
+        return fail(h, SSP_ESTATE, "virtual-stress correlator disabled (corr_levels = 0 or corr_virtual = 0)");
+    if (!Gv_dev || !Gv_err_dev) return fail(h, SSP_EINVAL, "Gv_dev and Gv_err_dev are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    double* batch = reinterpret_cast<double*>(h->work + h->lay.batch);
+    HIPCHK(h, launch_corr_batches(reinterpret_cast<const double*>(h->work + h->lay.acc_v), k.n_chains, k.corr_levels,
+                                  k.corr_batches, batch, s));
+    HIPCHK(h, launch_corr_final(batch, k.n_chains, k.corr_levels, k.corr_batches, h->corr_samples, Gv_dev, Gv_err_dev,
+                                s));
+    return check_flags(h, s);
+}
+
+int ssp_linear_viscoelasticity(ssp_handle* h, const double* G_dev, const double* omega_dev, int32_t n_omega,
+                               double t_lo, double t_hi, double* moduli_dev, double* scalars_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    const ssp_config& k = h->res.cfg;
+    if (k.corr_levels == 0) return fail(h, SSP_ESTATE, "correlator disabled (corr_levels = 0)");
+    if (!G_dev || !scalars_dev) return fail(h, SSP_EINVAL, "G_dev and scalars_dev are required");
+    if (n_omega < 0) return fail(h, SSP_EINVAL, "n_omega must be >= 0");
+    if (n_omega > 0 && (!omega_dev || !moduli_dev)) return fail(h, SSP_EINVAL, "omega_dev and moduli_dev are required");
+    if (!(t_lo <= t_hi)) return fail(h, SSP_EINVAL, "t_lo must not exceed t_hi");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, launch_moduli(G_dev, k.corr_levels, h->corr_samples, k.sample_every * k.dt, omega_dev, n_omega, t_lo, t_hi,
+                            moduli_dev, scalars_dev, s));
+    return SSP_OK;
+}
+
 int ssp_reset_observables(ssp_handle* h, ssp_stream stream)
 {
     if (!h) return SSP_EINVAL;
@@ -815,6 +871,7 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.kappa = kappa_dev;
             a.thr = reinterpret_cast<const uint32_t*>(h->work + h->lay.thr);
             a.thr_destroy = threshold(std::min(k.dt / k.zeta_s * 1.0, 1.0));
+            a.construct_rule = k.construct_rule;
             a.ph = h->phys();
             a.ctrl = sctrl;
             a.n_steps = (int32_t)m;

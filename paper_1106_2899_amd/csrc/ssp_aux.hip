@@ -161,8 +161,10 @@ __global__ void k_advance(int64_t* ctrl, int32_t n_steps, int32_t every, int64_t
 // one lane, adds x_l * y_l(n - k) to lane k, and is either parked as the
 // first of a pair or averaged with the parked value into a level-(l+1) value.
 // Histories start at zero, so unfilled lags add nothing; the number of
-// products per lag is known from the sample count.
-__global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
+// products per lag is known from the sample count.  With the virtual-stress
+// channel (V), x_v = sigma^v_ab(t) is paired with the same y history and
+// block-averaged like x.
+template <bool V> __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
 {
     const int64_t rows = 3 * a.n_chains;
     const int k = threadIdx.x & 15;
@@ -172,14 +174,16 @@ __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
     const int64_t chain = rr / 3;
     const int comp = (int)(rr % 3);
 
-    double yh[kMaxCorrLevels], C[kMaxCorrLevels];
+    double yh[kMaxCorrLevels], C[kMaxCorrLevels], Cv[V ? kMaxCorrLevels : 1];
 #pragma unroll
     for (int l = 0; l < kMaxCorrLevels; ++l) {
         yh[l] = (l < a.levels) ? a.hist[((int64_t)l * rows + rr) * 16 + k] : 0.0;
         C[l] = (l < a.levels) ? a.acc[((int64_t)l * rows + rr) * 16 + k] : 0.0;
+        if constexpr (V) Cv[l] = (l < a.levels) ? a.acc_v[((int64_t)l * rows + rr) * 16 + k] : 0.0;
     }
     double px = a.pend[(rr * 16 + k) * 2 + 0];
     double py = a.pend[(rr * 16 + k) * 2 + 1];
+    double pv = V ? a.pend_v[rr * 16 + k] : 0.0;
 
     const int64_t g0 = a.ctrl[kCtrlSteps];
     const int64_t s0 = a.ctrl[kCtrlCorrSamples];
@@ -187,7 +191,8 @@ __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
     for (int64_t q = 0; q < Q; ++q) {
         const double* smp = a.samples + (q * a.n_chains + chain) * kSampleValues;
         double xl = smp[3 + comp];
-        double yl = xl + smp[9 + comp];
+        double xv = smp[9 + comp];
+        double yl = xl + xv;
         const int64_t cnt1 = s0 + q + 1;  // 1-based index of this sample
         bool go = true;
 #pragma unroll
@@ -196,10 +201,12 @@ __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
                 const double prev = __shfl_up(yh[l], 1, 16);
                 yh[l] = (k == 0) ? yl : prev;
                 C[l] += xl * yh[l];
+                if constexpr (V) Cv[l] += xv * yh[l];
                 if ((cnt1 >> l) & 1) {  // first of a pair at this level: park it
                     if (k == l) {
                         px = xl;
                         py = yl;
+                        if constexpr (V) pv = xv;
                     }
                     go = false;
                 } else {
@@ -207,6 +214,7 @@ __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
                     const double qy = __shfl(py, l, 16);
                     xl = (qx + xl) * 0.5;
                     yl = (qy + yl) * 0.5;
+                    if constexpr (V) xv = (__shfl(pv, l, 16) + xv) * 0.5;
                 }
             }
         }
@@ -217,10 +225,12 @@ __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
         if (l < a.levels) {
             a.hist[((int64_t)l * rows + r) * 16 + k] = yh[l];
             a.acc[((int64_t)l * rows + r) * 16 + k] = C[l];
+            if constexpr (V) a.acc_v[((int64_t)l * rows + r) * 16 + k] = Cv[l];
         }
     }
     a.pend[(r * 16 + k) * 2 + 0] = px;
     a.pend[(r * 16 + k) * 2 + 1] = py;
+    if constexpr (V) a.pend_v[r * 16 + k] = pv;
 }
 
 // Batch sums of the accumulators: out[b][l][k] = sum over the chains of batch
@@ -475,7 +485,10 @@ hipError_t launch_advance(int64_t* ctrl, int32_t n_steps, int32_t sample_every, 
 hipError_t launch_corr(const CorrArgs& a, hipStream_t s)
 {
     const int64_t rows = 3 * a.n_chains;
-    hipLaunchKernelGGL(k_corr, dim3(blocks_for(rows, kBlock / 16)), dim3(kBlock), 0, s, a);
+    if (a.acc_v)
+        hipLaunchKernelGGL(k_corr<true>, dim3(blocks_for(rows, kBlock / 16)), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_corr<false>, dim3(blocks_for(rows, kBlock / 16)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ struct StepArgs {
     const double* kappa;   // [E][9]
     const uint32_t* thr;   // [2][kMaxBeads+1]: integer thresholds for p_K and 2 p_K
     uint32_t thr_destroy;
+    int32_t construct_rule;  // 0: K = C - Z attempts; 1: K = 1, the lowest empty slot attempts
     Physics ph;
     const int64_t* ctrl;
     int32_t n_steps;
@@ -100,6 +101,8 @@ struct CorrArgs {
     double* hist;           // [L][3M][16] lag history of y at each level
     double* acc;            // [L][3M][16] accumulated x(t) y(t - k)
     double* pend;           // [3M][16][2] pending (x, y) of level = lane
+    double* acc_v;          // [L][3M][16] accumulated x_v(t) y(t - k), x_v = sigma^v (or null: channel off)
+    double* pend_v;         // [3M][16] pending x_v of level = lane
     int64_t n_chains;
     int32_t levels;
     int32_t n_steps;
@@ -136,5 +139,7 @@ hipError_t launch_rec_s0(const int32_t* S, int8_t* rec, int64_t total, hipStream
 hipError_t launch_set_ctrl_steps(int64_t* ctrl, int64_t steps, hipStream_t s);
 hipError_t launch_rng_normals(int precision, uint32_t key0, uint32_t key1, uint32_t gid, int64_t step, int32_t bead,
                               int32_t count, double* out, hipStream_t s);
+hipError_t launch_moduli(const double* G, int32_t levels, int64_t samples, double sample_dt, const double* omega,
+                         int32_t n_omega, double t_lo, double t_hi, double* moduli, double* scalars, hipStream_t s);
 
 }  // namespace ssp

@@ -52,6 +52,8 @@ class Ensemble:
         series_capacity: int = 0,
         max_steps_per_launch: int = 0,
         use_graph: bool = True,
+        construct_rule: int = 0,
+        corr_virtual: bool = False,
         device: Union[str, torch.device, None] = None,
         stream: Optional[torch.cuda.Stream] = None,
     ):
@@ -94,6 +96,8 @@ class Ensemble:
         cfg.series_capacity = int(series_capacity)
         cfg.max_steps_per_launch = int(max_steps_per_launch)
         cfg.use_graph = 1 if use_graph else 0
+        cfg.construct_rule = int(construct_rule)  # 0: K = C - Z, 1: K = 1 (Sec. 3.2)
+        cfg.corr_virtual = 1 if corr_virtual else 0
         self.cfg = cfg
         self.dt, self.n0, self.ns, self.zeta_s, self.seed = cfg.dt, cfg.n0, cfg.ns, cfg.zeta_s, cfg.seed
         self.sample_every = cfg.sample_every
@@ -207,6 +211,40 @@ class Ensemble:
                                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self._s))
         return {"tau": tau.reshape(L, 16), "G": G.cpu().numpy().reshape(L, 16),
                 "G_err": E.cpu().numpy().reshape(L, 16), "counts": cnt.reshape(L, 16)}
+
+    def correlator_virtual(self):
+        """Virtual-stress channel: dict(tau, Gv, Gv_err) with
+        Gv = <sigma^v(t) [sigma + sigma^v](0)>, and dG_v = Gv / G, the relative
+        contribution of the virtual stress (Sec. 4.1), where G != 0."""
+        L = self.corr_levels
+        Gv = torch.empty(L * 16, dtype=torch.float64, device=self.device)
+        E = torch.empty(L * 16, dtype=torch.float64, device=self.device)
+        self._chk(lib().ssp_read_correlator_virtual(self._h, ctypes.c_void_p(Gv.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                                    self._s))
+        c = self.correlator()
+        gv = Gv.cpu().numpy().reshape(L, 16)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ratio = np.where(c["G"] != 0.0, gv / c["G"], np.nan)
+        return {"tau": c["tau"], "Gv": gv, "Gv_err": E.cpu().numpy().reshape(L, 16), "counts": c["counts"],
+                "dG_v": ratio}
+
+    def linear_viscoelasticity(self, omega, t_lo: float, t_hi: float, G=None):
+        """G'(w), G''(w), |eta*(w)|, eta_0 and tau_d from the relaxation modulus
+        (Sec. 4.1 relations), computed on the device; G defaults to the
+        correlator's current G(t) ([levels*16] FP64 on the device)."""
+        if G is None:
+            G = torch.as_tensor(self.correlator()["G"].ravel(), dtype=torch.float64, device=self.device)
+        G = G.to(device=self.device, dtype=torch.float64).contiguous()
+        w = torch.as_tensor(np.asarray(omega, dtype=np.float64), device=self.device).contiguous()
+        moduli = torch.empty((w.numel(), 3), dtype=torch.float64, device=self.device)
+        scalars = torch.empty(2, dtype=torch.float64, device=self.device)
+        self._chk(lib().ssp_linear_viscoelasticity(self._h, ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                                   int(w.numel()), float(t_lo), float(t_hi),
+                                                   ctypes.c_void_p(moduli.data_ptr()),
+                                                   ctypes.c_void_p(scalars.data_ptr()), self._s))
+        m, sc = moduli.cpu().numpy(), scalars.cpu().numpy()
+        return {"omega": w.cpu().numpy(), "Gp": m[:, 0], "Gpp": m[:, 1], "eta_abs": m[:, 2],
+                "eta0": float(sc[0]), "tau_d": float(sc[1])}
 
     def reset_observables(self) -> "Ensemble":
         self._chk(lib().ssp_reset_observables(self._h, self._s))

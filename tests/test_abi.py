@@ -48,6 +48,7 @@ def test_defaults_are_the_paper_parameters():
     c = _cfg(L)
     assert (c.n0, c.ns, c.zeta_s, c.dt) == (4.0, 0.5, 0.1, 0.01)
     assert c.precision == L.SSP_FP32 and c.corr_levels == 16 and c.corr_lags == 16
+    assert c.construct_rule == 0  # K = C - Z, the GPU rule of Sec. 3.2
 
 
 def test_query_sizes_valid_and_scaling():
@@ -72,6 +73,7 @@ def test_query_sizes_valid_and_scaling():
     ("corr_levels", 17, "corr_levels"),
     ("corr_lags", 8, "corr_lags"),
     ("series_capacity", -1, "series_capacity"),
+    ("construct_rule", 2, "construct_rule"),
     ("n_elements", 0, "n_elements"),
 ])
 def test_invalid_configs_are_rejected(field, value, msg):

@@ -23,15 +23,17 @@ def _ens(N, M=None, **kw):
     return Ensemble(N, M, **kw)
 
 
-def _oracle_G(samples, levels):
-    """G[l][k] = sum over chains and xy, yz, zx of C / (3 M cnt)."""
+def _oracle_G(samples, levels, virtual=False):
+    """G[l][k] = sum over chains and xy, yz, zx of C / (3 M cnt), C the
+    multiple-tau correlation of x = sigma (virtual: x = sigma^v) with
+    y = sigma + sigma^v."""
     T, M, _ = samples.shape
     tot = np.zeros((levels, 16))
     cnt = None
     for k in range(M):
         for c in range(3):
-            x = samples[:, k, 3 + c]
-            y = x + samples[:, k, 9 + c]
+            x = samples[:, k, (9 if virtual else 3) + c]
+            y = samples[:, k, 3 + c] + samples[:, k, 9 + c]
             C, n = oracle.multitau(x, y, levels=levels, lags=16)
             tot += C
             cnt = n
@@ -72,6 +74,30 @@ def test_correlator_matches_oracle_fp64():
     np.testing.assert_allclose(got["G"], G, rtol=1e-9, atol=1e-11)
     np.testing.assert_allclose(got["tau"][0], np.arange(16) * every * 0.01)
     assert np.all(got["G_err"][cnt > 0] >= 0)
+
+
+def test_virtual_stress_channel_matches_oracle_fp64():
+    """The corr_virtual channel <sigma^v(t) [sigma + sigma^v](0)> and the
+    relative virtual-stress contribution Gv / G (Sec. 4.1) against the
+    oracle's multiple-tau correlation of the same samples; turning the channel
+    on leaves G(t) unchanged."""
+    M, N, every, steps, L = 32, 8, 3, 3000, 10
+    e = _ens(N, M, precision="fp64", seed=6, sample_every=every, corr_levels=L, corr_batches=4,
+             corr_virtual=True).init()
+    e.step(steps)
+    got = e.correlator_virtual()
+    o = oracle.Ensemble([N] * M, seed=6).init()
+    s = o.run(steps, sample_every=every)
+    Gv, cnt = _oracle_G(s, L, virtual=True)
+    G, _ = _oracle_G(s, L)
+    np.testing.assert_allclose(got["Gv"], Gv, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(e.correlator()["G"], G, rtol=1e-9, atol=1e-11)
+    ok = (cnt > 0) & (np.abs(G) > 1e-3)
+    np.testing.assert_allclose(got["dG_v"][ok], Gv[ok] / G[ok], rtol=1e-8)
+    assert np.all(got["Gv_err"][cnt > 0] >= 0)
+    plain = _ens(N, M, precision="fp64", seed=6, sample_every=every, corr_levels=L, corr_batches=4).init()
+    with pytest.raises(Exception):
+        plain.correlator_virtual()
 
 
 def test_correlator_matches_oracle_fp32_statistically_close():

@@ -89,9 +89,9 @@ def test_init_matches_oracle(precision):
 
 # --------------------------------------------------- step-by-step parity ---
 
-def _stepwise(precision, M, N, steps, kappa=None, seed=3):
-    e = _ens(N, M, precision=precision, seed=seed, corr_levels=0).init()
-    o = oracle.Ensemble([N] * M, seed=seed).init()
+def _stepwise(precision, M, N, steps, kappa=None, seed=3, construct_rule=0):
+    e = _ens(N, M, precision=precision, seed=seed, corr_levels=0, construct_rule=construct_rule).init()
+    o = oracle.Ensemble([N] * M, seed=seed, construct_rule=construct_rule).init()
     kap = None if kappa is None else np.asarray(kappa)
     alive = np.ones(M, dtype=bool)
     ties = 0
@@ -140,4 +140,19 @@ def test_stepwise_parity_fp32_256x32():
 def test_stepwise_parity_fp32_shear_128x16():
     worst, ties, alive = _stepwise("fp32", 128, 16, 500, kappa=[[0, 0.3, 0], [0, 0, 0], [0, 0, 0]], seed=9)
     print("fp32 128x16 shear worst rel err", worst, "ties", ties)
+    assert alive >= 120
+
+
+# ------------------------------------- K = 1 construction rule (Sec. 3.2) ---
+
+def test_stepwise_parity_cpu_construction_rule_fp64():
+    worst, ties, _ = _stepwise("fp64", 64, 8, 1000, construct_rule=1, seed=13)
+    print("fp64 64x8 K=1 worst rel err", worst)
+    assert ties == 0
+
+
+def test_stepwise_parity_cpu_construction_rule_fp32_shear():
+    worst, ties, alive = _stepwise("fp32", 128, 16, 500, kappa=[[0, 0.3, 0], [0, 0, 0], [0, 0, 0]], seed=14,
+                                   construct_rule=1)
+    print("fp32 128x16 K=1 shear worst rel err", worst, "ties", ties)
     assert alive >= 120

@@ -339,17 +339,19 @@ def test_rouse_mean_normal_stress_closed_form(rouse_run):
 
 # ------------------------------------------ N = 2: exact slot Markov chain ---
 
-def n2_stationary(dt=DT, n0=N0, zeta_s=ZS):
+def n2_stationary(dt=DT, n0=N0, zeta_s=ZS, rule=0):
     """Z of a 2-bead chain is an autonomous Markov chain (both beads are ends):
-    each occupied slot is destroyed with min(dt/zeta_s, 1); each of the
-    K = 2 - Z empty slots creates with probability 2 min(dt/(zeta_s n0 K), 1/2);
-    springs created in the step are not destroyed in it."""
+    each occupied slot is destroyed with min(dt/zeta_s, 1); springs created in
+    the step are not destroyed in it.  Rule 0 (GPU rule, Sec. 3.2): each of the
+    K = 2 - Z empty slots creates with probability 2 min(dt/(zeta_s n0 K), 1/2).
+    Rule 1 (CPU rule, K = 1): one attempt while a slot is empty, creating with
+    probability 2 min(dt/(zeta_s n0), 1/2)."""
     from math import comb
     cd = min(dt / zeta_s, 1.0)
     P = np.zeros((3, 3))
     for z in range(3):
-        K = 2 - z
-        q = 2.0 * min(dt / (zeta_s * n0 * K), 0.5) if K > 0 else 0.0
+        K = 2 - z if rule == 0 else (1 if z < 2 else 0)
+        q = 2.0 * min(dt / (zeta_s * n0 * (K if rule == 0 else 1)), 0.5) if K > 0 else 0.0
         for d in range(z + 1):
             pd = comb(z, d) * cd**d * (1 - cd) ** (z - d)
             for c in range(K + 1):
@@ -375,6 +377,53 @@ def test_n2_stationary_law_of_z():
     for z in range(3):
         est, se = _batch_se(frac[:, z])
         assert abs(est - pi[z]) < 4.0 * se + 1e-4, (z, est, pi[z], se)
+
+
+def test_n2_stationary_law_of_z_cpu_rule_and_detailed_balance_comparison():
+    """The K = 1 construction rule (Sec. 3.2, CPU) as a variant: the oracle's
+    N = 2 chains follow that rule's exact law, which differs from the GPU
+    rule's; both approach the equilibrium law (Poisson(N/N0) truncated to
+    0..2) linearly in dt, the K = 1 rule with about twice the bias."""
+    pi1 = n2_stationary(rule=1)
+    np.testing.assert_allclose(pi1, [0.611570, 0.314050, 0.074380], atol=2e-6)
+    eq = np.array([1.0, 0.5, 0.125])
+    eq /= eq.sum()
+    bias = {}
+    for dt in (0.01, 0.005, 0.0025):
+        bias[dt] = [np.abs(n2_stationary(dt=dt, rule=r) - eq).max() for r in (0, 1)]
+    for r in (0, 1):  # O(dt): halving dt halves the bias
+        assert bias[0.005][r] / bias[0.01][r] == pytest.approx(0.5, abs=0.02)
+        assert bias[0.0025][r] / bias[0.005][r] == pytest.approx(0.5, abs=0.02)
+    assert bias[0.01][1] == pytest.approx(2.0 * bias[0.01][0], rel=0.05)
+
+    M = 20000
+    e = oracle.Ensemble([2] * M, seed=33, construct_rule=1).init()
+    e.run(300, keep_samples=False)
+    Zt = []
+    for _ in range(60):
+        e.run(25, keep_samples=False)
+        Zt.append((e.S.reshape(M, 2) >= 0).sum(axis=1))
+    Zt = np.array(Zt)
+    frac = np.stack([(Zt == z).mean(axis=0) for z in range(3)], axis=1)
+    pi0 = n2_stationary(rule=0)
+    est1, se1 = _batch_se(frac[:, 1])
+    for z in range(3):
+        est, se = _batch_se(frac[:, z])
+        assert abs(est - pi1[z]) < 4.0 * se + 1e-4, (z, est, pi1[z], se)
+    # at most one spring is created per step
+    e2 = oracle.Ensemble([8] * 2000, seed=34, construct_rule=1).init()
+    for _ in range(50):
+        before = e2.S.reshape(2000, 8) >= 0
+        ev, _ = e2.step(want_events=True)
+        created = (ev.reshape(2000, 8) & (oracle.EV_CREATE_FIRST | oracle.EV_CREATE_LAST)) > 0
+        assert created.sum(axis=1).max() <= 1
+        # ... and only by the lowest slot empty after the hops (hops keep the
+        # occupancy, so that is the lowest slot empty at the start of the step)
+        rows = np.nonzero(created.any(axis=1))[0]
+        for r in rows:
+            j = int(np.nonzero(created[r])[0][0])
+            assert j == int(np.nonzero(~before[r])[0][0])
+    assert abs(est1 - pi0[1]) > 3.0 * se1  # the two rules are distinguishable here
 
 
 # ---------------------------------------- equilibrium with springs on ------
@@ -440,6 +489,29 @@ def test_step_strain_response_equals_green_kubo_with_virtual_stress():
     r_est, r_se = _batch_se(resp[L])
     g_plain, gp_se = gk(L + 1, x)
     assert abs(r_est - g_plain) > 4.0 * math.hypot(r_se, gp_se), results
+
+
+def test_virtual_stress_contribution_at_zero_lag():
+    """At t = 0 in equilibrium (the exact sampler, no dt bias) the two halves of
+    the relative virtual-stress contribution (Sec. 4.1) have closed forms:
+    the anchor offsets d_j are N(0, N_s/3) and independent of the bonds, so
+    <sigma^v_xy (sigma + sigma^v)_xy> = (3/N_s)^2 <Z> (N_s/3)^2 = <Z> and
+    <sigma_xy (sigma + sigma^v)_xy> = 9 (N-1) (1/3)^2 = N - 1; the same for yz
+    and zx.  (For N = 8 the ratio <Z>/(N-1) = 0.286 is of the 25 % size the
+    paper reports.)"""
+    N, M = 8, 20000
+    e = oracle.Ensemble([N] * M, seed=57).init()
+    st = e.stress()
+    Z = (e.S.reshape(M, N) >= 0).sum(axis=1)
+    for c in range(3):
+        sig, sv = st[:, 3 + c], st[:, 9 + c]
+        num, num_se = _batch_se(sv * (sig + sv))
+        den, den_se = _batch_se(sig * (sig + sv))
+        assert abs(num - Z.mean()) < 4.0 * num_se, (c, num, Z.mean(), num_se)
+        assert abs(den - (N - 1)) < 4.0 * den_se, (c, den, N - 1, den_se)
+    lam = N / N0
+    pz = np.array([math.exp(-lam) * lam**z / math.factorial(z) for z in range(N + 1)])
+    assert Z.mean() == pytest.approx((pz * np.arange(N + 1)).sum() / pz.sum(), abs=4.0 * Z.std() / math.sqrt(M))
 
 
 # -------------------------------------------------- multiple-tau correlator --
