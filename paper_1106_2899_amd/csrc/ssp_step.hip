@@ -58,50 +58,22 @@ template <typename T> __device__ __forceinline__ void st3(void* base, int64_t id
     reinterpret_cast<typename Vec4<T>::type*>(base)[idx] = o;
 }
 
-// Per-bead record staged in LDS after the move: R hi, R lo (FP32 only: the
-// FP64 path has no lo part), bond to the right, bond from the left, and the
-// move increment of the step.
-template <typename T> struct RecLayout {
-    static constexpr bool kComp = std::is_same<T, float>::value;
-    static constexpr int kRh = 0, kRl = 3, kBr = kComp ? 6 : 3, kBl = kBr + 3, kInc = kBl + 3;
-    static constexpr int kLen = kComp ? 16 : 12;
-};
+// Per-bead record staged in LDS: R hi, R lo, bond to the right, bond from the left.
 template <typename T> struct alignas(16) BeadRec {
-    T v[RecLayout<T>::kLen];
+    T v[12];
 };
-template <typename T> __device__ __forceinline__ v3<T> rec3(const BeadRec<T>& r, int o)
-{
-    return {r.v[o], r.v[o + 1], r.v[o + 2]};
-}
-template <typename T> __device__ __forceinline__ v3<T> rec_rl(const BeadRec<T>& r)
-{
-    if constexpr (RecLayout<T>::kComp)
-        return rec3(r, RecLayout<T>::kRl);
-    else
-        return zero3<T>();
-}
 template <typename T> struct alignas(16) Off4 {
     T v[4];
 };
 
 template <typename T>
-__device__ __forceinline__ void rec_put(BeadRec<T>& r, v3<T> rh, v3<T> rl, v3<T> br, v3<T> bl, v3<T> inc)
+__device__ __forceinline__ void rec_put(BeadRec<T>& r, v3<T> rh, v3<T> rl, v3<T> br, v3<T> bl)
 {
-    using L = RecLayout<T>;
     BeadRec<T> t;
-    auto put = [&](int o, v3<T> x) {
-        t.v[o] = x.x;
-        t.v[o + 1] = x.y;
-        t.v[o + 2] = x.z;
-    };
-    put(L::kRh, rh);
-    if constexpr (L::kComp) {
-        put(L::kRl, rl);
-        t.v[15] = T(0);
-    }
-    put(L::kBr, br);
-    put(L::kBl, bl);
-    put(L::kInc, inc);
+    t.v[0] = rh.x; t.v[1] = rh.y; t.v[2] = rh.z;
+    t.v[3] = rl.x; t.v[4] = rl.y; t.v[5] = rl.z;
+    t.v[6] = br.x; t.v[7] = br.y; t.v[8] = br.z;
+    t.v[9] = bl.x; t.v[10] = bl.y; t.v[11] = bl.z;
     r = t;
 }
 
@@ -123,11 +95,6 @@ __device__ __forceinline__ uint32_t lds_load(uint32_t* p)
 __device__ __forceinline__ void lds_min(uint32_t* p, uint32_t v)
 {
     __hip_atomic_fetch_min(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-
-template <typename T> __device__ __forceinline__ void lds_add(T* p, T v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
@@ -158,14 +125,11 @@ template <typename T, int B> struct WaveLds {
     uint32_t first[kWaveSize * B];
 };
 
-// Register budget of the step kernel (waves per SIMD the allocator must
-// allow): FP32 fits 128 VGPRs with one bead per lane (4 waves) and 168 with
-// two (3 waves); FP64 fits 256 (2 waves).
-template <typename T, int B>
-constexpr int kStepWavesPerEu = std::is_same<T, float>::value ? (B == 1 ? 4 : 3) : 2;
-
-template <typename T, int W, int B>
-__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>))) k_step(StepArgs a)
+// K1: construction by the K = 1 rule (one attempt per chain and step, by the
+// lowest empty slot) instead of K = C - Z; a template parameter so that
+// neither kernel carries the other rule's work.
+template <typename T, int W, int B, bool K1>
+__global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 {
     constexpr bool kComp = std::is_same<T, float>::value;  // (hi, lo) position sums
     constexpr int kChainsPerWave = kWaveSize / W;
@@ -193,10 +157,6 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
     BeadRec<T>* rec = reinterpret_cast<BeadRec<T>*>(lds[wv].shared);
     double* sums = reinterpret_cast<double*>(lds[wv].shared);
     Off4<T>* offs = lds[wv].off;
-    // spring-force accumulators: overlay the bead records, which are not live
-    // during the force gather
-    Off4<T>* facc = reinterpret_cast<Off4<T>*>(lds[wv].shared);
-    static_assert(sizeof(Off4<T>) * kWaveSize * B <= sizeof(lds[0].shared), "accumulators must fit the record area");
     const int lbase = seg * kCap;  // this segment's first entry in the LDS arrays
 
     // Step constants with dt folded in: the move is
@@ -240,9 +200,6 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
     // Bonds to the right neighbour (br) and from the left neighbour (bl) of
     // every bead owned by the lane (zero past the chain ends), then the bead
     // records in LDS.
-    v3<T> minc[B];  // move increment of each bead in the current step
-#pragma unroll
-    for (int b = 0; b < B; ++b) minc[b] = zero3<T>();
     auto bonds_and_records = [&]() {
         const v3<T> nh = from_next3(rh[0]);
         const v3<T> nl = from_next3(rl[0]);
@@ -263,7 +220,7 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
 #pragma unroll
         for (int b = 0; b < B; ++b) bl[b] = (b > 0) ? br[b > 0 ? b - 1 : 0] : left;
 #pragma unroll
-        for (int b = 0; b < B; ++b) rec_put(rec[lbase + li * B + b], rh[b], rl[b], br[b], bl[b], minc[b]);
+        for (int b = 0; b < B; ++b) rec_put(rec[lbase + li * B + b], rh[b], rl[b], br[b], bl[b]);
         wave_sync();
     };
 
@@ -276,8 +233,8 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
         for (int b = 0; b < B; ++b) {
             const int t = s[b] > 0 ? s[b] : 0;
             const BeadRec<T> r = rec[lbase + t];
-            const v3<T> Rh = rec3(r, RecLayout<T>::kRh);
-            const v3<T> Rl = rec_rl(r);
+            const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
+            const v3<T> Rl = {r.v[3], r.v[4], r.v[5]};
             d[b] = (s[b] >= 0) ? ((Rh - ah[b]) + (Rl - al[b])) : zero3<T>();
             Off4<T> o;
             o.v[0] = d[b].x;
@@ -348,47 +305,15 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
         const bool even = (g & 1) == 0;  // wave-uniform
         const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
 
-        // ---- substep 1a: slip-spring force, the sum of d_j over the springs
-        // of each bead.  Every spring adds its d_j into its bead's LDS
-        // accumulator (hardware float adds) and counts itself in the fourth
-        // word.  A sum of at most two terms onto zero is the same in any order
-        // of the adds, so this result is deterministic; a wave in which some
-        // bead carries three or more springs redoes the sums below in
-        // increasing slot order.  Beads with one or two springs get the same
-        // value either way, so trajectories do not depend on which chains
-        // share a wave.
+        // ---- substep 1a: slip-spring force, sum of d_j over the springs of each
+        // bead, delivered in increasing slot order (one spring per bead per round).
         v3<T> acc[B];
-        bool many = false;
-#pragma unroll
-        for (int b = 0; b < B; ++b) facc[lbase + li * B + b] = Off4<T>{{T(0), T(0), T(0), T(0)}};
-        wave_sync();
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            if (s[b] >= 0) {
-                T* q = facc[lbase + s[b]].v;
-                lds_add(q + 0, d[b].x);
-                lds_add(q + 1, d[b].y);
-                lds_add(q + 2, d[b].z);
-                lds_add(q + 3, T(1));
-            }
-        }
-        wave_sync();
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const Off4<T> o = facc[lbase + li * B + b];
-            acc[b] = v3<T>{o.v[0], o.v[1], o.v[2]};
-            many |= o.v[3] > T(2.5);
-        }
-        // Ordered gather: in rounds, pending springs ds_min their slot index into
-        // their bead's word and each bead adds the winner's d (one spring per
-        // bead per round, in increasing slot order).
         bool pend[B];
         bool any_pend = false;
-        const bool ordered = wave_any(many);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            pend[b] = ordered && s[b] >= 0;
-            if (ordered) acc[b] = zero3<T>();
+            acc[b] = zero3<T>();
+            pend[b] = s[b] >= 0;
             any_pend |= pend[b];
         }
         // Every round delivers at least one spring per bead that still has one,
@@ -435,7 +360,6 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
             inc = fma3(-cspring, acc[b], inc);
             // wave-uniform branch; fma(0, r, x) = x keeps chains without flow bit-identical
             if (flow) inc = fma_mat3(kdt, rh[b], inc);
-            minc[b] = inc;
             if (i < n) {
                 if constexpr (kComp)
                     cadd3(rh[b], rl[b], inc);
@@ -478,15 +402,11 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
             }
             const int t = s[b] > 0 ? s[b] : 0;
             const BeadRec<T> r = rec[lbase + t];
-            const v3<T> bp = rec3(r, RecLayout<T>::kBr);   // R_{S+1} - R_S
-            const v3<T> bm = -rec3(r, RecLayout<T>::kBl);  // R_{S-1} - R_S
-            // post-move offset R_S - A: without flow, the offset at the start of
-            // the step (its LDS copy) plus the move increment of bead S; a chain
-            // with flow (per chain, so that wave-mates do not matter) takes it
-            // from the compensated positions
-            const Off4<T> o = offs[lbase + li * B + b];
-            v3<T> dd = v3<T>{o.v[0], o.v[1], o.v[2]} + rec3(r, RecLayout<T>::kInc);
-            if (flow && has_flow) dd = (rec3(r, RecLayout<T>::kRh) - ah[b]) + (rec_rl(r) - al[b]);
+            const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
+            const v3<T> Rl = {r.v[3], r.v[4], r.v[5]};
+            const v3<T> bp = {r.v[6], r.v[7], r.v[8]};      // R_{S+1} - R_S
+            const v3<T> bm = {-r.v[9], -r.v[10], -r.v[11]};  // R_{S-1} - R_S
+            const v3<T> dd = (Rh - ah[b]) + (Rl - al[b]);
             // (R_{S+-1} - A)^2 - (R_S - A)^2 = b (b + 2 d) with b = R_{S+-1} - R_S
             const T up = dot(bp, bp + T(2) * dd);
             const T dn = dot(bm, bm + T(2) * dd);
@@ -509,12 +429,12 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             z += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
-            if (a.construct_rule == 1) {
+            if constexpr (K1) {
                 const uint64_t m = __ballot(s[b] < 0 && li * B + b < n) & seg_mask<W>(sb);
                 if (m) first_empty = min(first_empty, ((int)__builtin_ctzll(m) - sb) * B + b);
             }
         }
-        const int K = a.construct_rule == 1 ? (z < n ? 1 : 0) : n - z;
+        const int K = K1 ? (z < n ? 1 : 0) : n - z;
         const uint32_t t1 = thr[K < 0 ? 0 : K];
         const uint32_t t2 = thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
         int create_at[B];
@@ -527,7 +447,7 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
             if (j < n) {
                 if (s[b] >= 0) {
                     if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) s[b] = -1;
-                } else if (a.construct_rule == 0 || j == first_empty) {
+                } else if (!K1 || j == first_empty) {
                     if (uw < t1)
                         create_at[b] = 0;
                     else if (uw < t2)
@@ -542,8 +462,8 @@ __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per
                 const int j = li * B + b;
                 if (create_at[b] >= 0) {
                     const BeadRec<T> r = rec[lbase + create_at[b]];
-                    const v3<T> Rh = rec3(r, RecLayout<T>::kRh);
-                    const v3<T> Rl = rec_rl(r);
+                    const v3<T> Rh = {r.v[0], r.v[1], r.v[2]};
+                    const v3<T> Rl = {r.v[3], r.v[4], r.v[5]};
                     const v3<T> off3 = asd * normals3<T>(draw(kAnchor, (uint32_t)j, gid, g, k0, k1));
                     if constexpr (kComp) {
                         ah[b] = Rh;
@@ -633,7 +553,10 @@ template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipSt
     constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
     const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
     if (groups == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_step<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    if (a.construct_rule == 1)
+        hipLaunchKernelGGL((k_step<T, W, B, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step<T, W, B, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     return hipGetLastError();
 }
 
