@@ -203,7 +203,7 @@ def main():
     kernel_src = os.path.join(ROOT, "paper_1106_2899_amd", "csrc", "ssp_step.hip")
     roofline = {
         "bound": "alu",
-        "kernel": "k_step<float,32,1>",
+        "kernel": "k_step<float,32,1,false>",
         "achieved": achieved,
         "peak": PEAK_LANE_SLOTS,
         "unit": "VALU lane-slots/s",
