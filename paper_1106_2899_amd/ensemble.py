@@ -174,6 +174,12 @@ class Ensemble:
         self._chk(lib().ssp_read_stress(self._h, ctypes.c_void_p(out.data_ptr()), self._s))
         return out
 
+    def step_count(self) -> int:
+        """Steps completed since init()."""
+        n = ctypes.c_int64()
+        self._chk(lib().ssp_step_count(self._h, ctypes.byref(n)))
+        return int(n.value)
+
     def state(self):
         """Canonical FP64 state: R [sumN,3], A [sumN,3], S [sumN] (-1 = empty slot)."""
         R = torch.empty((self.total_beads, 3), dtype=torch.float64, device=self.device)
