@@ -65,6 +65,7 @@ template <typename T> struct alignas(16) BeadRec {
 template <typename T> struct alignas(16) Off4 {
     T v[4];
 };
+template <typename T> __device__ __forceinline__ v3<T> unpack3(const Off4<T>& o) { return {o.v[0], o.v[1], o.v[2]}; }
 
 template <typename T>
 __device__ __forceinline__ void rec_put(BeadRec<T>& r, v3<T> rh, v3<T> rl, v3<T> br, v3<T> bl)
@@ -306,7 +307,10 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
 
         // ---- substep 1a: slip-spring force, sum of d_j over the springs of each
-        // bead, delivered in increasing slot order (one spring per bead per round).
+        // bead, delivered in increasing slot order (one spring per bead per
+        // round).  The first round's LDS operations are issued before the
+        // step's noise is computed (it does not depend on them), so that their
+        // latency runs under that arithmetic.
         v3<T> acc[B];
         bool pend[B];
         bool any_pend = false;
@@ -316,15 +320,56 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             pend[b] = s[b] >= 0;
             any_pend |= pend[b];
         }
-        // Every round delivers at least one spring per bead that still has one,
-        // so kCap rounds always suffice; the cap only guards against a hang.
-        for (int round = 0; round <= kCap && wave_any(any_pend); ++round) {
+        const bool gather = wave_any(any_pend);
+        uint32_t got[B], chk[B];
+        if (gather) {
 #pragma unroll
             for (int b = 0; b < B; ++b) lds_store(&lfirst[lbase + li * B + b], 0xFFFFFFFFu);
 #pragma unroll
             for (int b = 0; b < B; ++b)
                 if (pend[b]) lds_min(&lfirst[lbase + s[b]], (uint32_t)(lbase + li * B + b));
-            uint32_t got[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                got[b] = lds_load(&lfirst[lbase + li * B + b]);
+                chk[b] = lds_load(&lfirst[lbase + (s[b] > 0 ? s[b] : 0)]);
+            }
+        }
+
+        // ---- substep 1b, first part: sqrt(2 dt) w of this step.
+        v3<T> noise[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            if (even) {
+                const uint4 x = draw(kNoise, (uint32_t)i, gid, kp, k0, k1);
+                box_muller(x.x, x.y, cnoise, noise[b].x, noise[b].y);
+                box_muller(x.z, x.w, cnoise, noise[b].z, carry_n[b]);
+            } else {
+                noise[b].x = carry_n[b];
+                box_muller(carry_w0[b], carry_w1[b], cnoise, noise[b].y, noise[b].z);
+            }
+        }
+
+        // ---- substep 1a, completion of the first round and further rounds.
+        // Every round delivers at least one spring per bead that still has
+        // one, so kCap rounds always suffice; the cap only guards against a hang.
+        if (gather) {
+            any_pend = false;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (pend[b] && chk[b] == (uint32_t)(lbase + li * B + b)) pend[b] = false;
+                any_pend |= pend[b];
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (got[b] != 0xFFFFFFFFu) acc[b] = acc[b] + unpack3(offs[got[b]]);
+        }
+        for (int round = 1; round <= kCap && wave_any(any_pend); ++round) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) lds_store(&lfirst[lbase + li * B + b], 0xFFFFFFFFu);
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (pend[b]) lds_min(&lfirst[lbase + s[b]], (uint32_t)(lbase + li * B + b));
 #pragma unroll
             for (int b = 0; b < B; ++b) got[b] = lds_load(&lfirst[lbase + li * B + b]);
             any_pend = false;
@@ -334,12 +379,8 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
                 any_pend |= pend[b];
             }
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (got[b] != 0xFFFFFFFFu) {
-                    const Off4<T> o = offs[got[b]];
-                    acc[b] = acc[b] + v3<T>{o.v[0], o.v[1], o.v[2]};
-                }
-            }
+            for (int b = 0; b < B; ++b)
+                if (got[b] != 0xFFFFFFFFu) acc[b] = acc[b] + unpack3(offs[got[b]]);
         }
         if (any_pend) atomicOr(a.flags, kFlagInternal);
 
@@ -347,15 +388,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
-            v3<T> inc;  // sqrt(2 dt) w
-            if (even) {
-                const uint4 x = draw(kNoise, (uint32_t)i, gid, kp, k0, k1);
-                box_muller(x.x, x.y, cnoise, inc.x, inc.y);
-                box_muller(x.z, x.w, cnoise, inc.z, carry_n[b]);
-            } else {
-                inc.x = carry_n[b];
-                box_muller(carry_w0[b], carry_w1[b], cnoise, inc.y, inc.z);
-            }
+            v3<T> inc = noise[b];
             inc = fma3(cbond, br[b] - bl[b], inc);
             inc = fma3(-cspring, acc[b], inc);
             // wave-uniform branch; fma(0, r, x) = x keeps chains without flow bit-identical
