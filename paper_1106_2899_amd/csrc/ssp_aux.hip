@@ -164,6 +164,47 @@ __global__ void k_advance(int64_t* ctrl, int32_t n_steps, int32_t every, int64_t
 // products per lag is known from the sample count.  With the virtual-stress
 // channel (V), x_v = sigma^v_ab(t) is paired with the same y history and
 // block-averaged like x.
+//
+// The row is a DPP row (16 lanes): the history shift is row_shr:1 and the
+// parked pair of level l is read with row_newbcast:l, so the level loop runs
+// without LDS traffic (DPP controls are immediates: the level loop is fully
+// unrolled).
+__device__ __forceinline__ double row_shr1(double v)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_mov_dpp(p.x, 0x111, 0xf, 0xf, true),
+                                                __builtin_amdgcn_mov_dpp(p.y, 0x111, 0xf, 0xf, true)));
+}
+template <int L> __device__ __forceinline__ double row_bcast(double v)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_mov_dpp(p.x, 0x150 + L, 0xf, 0xf, true),
+                                                __builtin_amdgcn_mov_dpp(p.y, 0x150 + L, 0xf, 0xf, true)));
+}
+// row_bcast<l> for a level index that is a constant once the level loop is
+// unrolled (the switch folds away).
+__device__ __forceinline__ double row_bcast_level(double v, int l)
+{
+    switch (l) {
+    case 0: return row_bcast<0>(v);
+    case 1: return row_bcast<1>(v);
+    case 2: return row_bcast<2>(v);
+    case 3: return row_bcast<3>(v);
+    case 4: return row_bcast<4>(v);
+    case 5: return row_bcast<5>(v);
+    case 6: return row_bcast<6>(v);
+    case 7: return row_bcast<7>(v);
+    case 8: return row_bcast<8>(v);
+    case 9: return row_bcast<9>(v);
+    case 10: return row_bcast<10>(v);
+    case 11: return row_bcast<11>(v);
+    case 12: return row_bcast<12>(v);
+    case 13: return row_bcast<13>(v);
+    case 14: return row_bcast<14>(v);
+    default: return row_bcast<15>(v);
+    }
+}
+
 template <bool V> __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
 {
     const int64_t rows = 3 * a.n_chains;
@@ -188,17 +229,30 @@ template <bool V> __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
     const int64_t g0 = a.ctrl[kCtrlSteps];
     const int64_t s0 = a.ctrl[kCtrlCorrSamples];
     const int64_t Q = samples_in(g0, a.n_steps, a.sample_every);
+    // the values of the next two samples are in flight while one is processed
+    auto load = [&](int64_t q, double& x, double& v) {
+        if (q < Q) {
+            const double* smp = a.samples + (q * a.n_chains + chain) * kSampleValues;
+            x = smp[3 + comp];
+            v = smp[9 + comp];
+        }
+    };
+    double nx0 = 0.0, nv0 = 0.0, nx1 = 0.0, nv1 = 0.0;
+    load(0, nx0, nv0);
+    load(1, nx1, nv1);
     for (int64_t q = 0; q < Q; ++q) {
-        const double* smp = a.samples + (q * a.n_chains + chain) * kSampleValues;
-        double xl = smp[3 + comp];
-        double xv = smp[9 + comp];
+        double xl = nx0;
+        double xv = nv0;
+        nx0 = nx1;
+        nv0 = nv1;
+        load(q + 2, nx1, nv1);
         double yl = xl + xv;
         const int64_t cnt1 = s0 + q + 1;  // 1-based index of this sample
         bool go = true;
 #pragma unroll
         for (int l = 0; l < kMaxCorrLevels; ++l) {
             if (go && l < a.levels) {
-                const double prev = __shfl_up(yh[l], 1, 16);
+                const double prev = row_shr1(yh[l]);
                 yh[l] = (k == 0) ? yl : prev;
                 C[l] += xl * yh[l];
                 if constexpr (V) Cv[l] += xv * yh[l];
@@ -210,11 +264,11 @@ template <bool V> __global__ void __launch_bounds__(kBlock) k_corr(CorrArgs a)
                     }
                     go = false;
                 } else {
-                    const double qx = __shfl(px, l, 16);
-                    const double qy = __shfl(py, l, 16);
+                    const double qx = row_bcast_level(px, l);
+                    const double qy = row_bcast_level(py, l);
                     xl = (qx + xl) * 0.5;
                     yl = (qy + yl) * 0.5;
-                    if constexpr (V) xv = (__shfl(pv, l, 16) + xv) * 0.5;
+                    if constexpr (V) xv = (row_bcast_level(pv, l) + xv) * 0.5;
                 }
             }
         }
