@@ -204,8 +204,8 @@ int ssp_step_count(const ssp_handle* h, int64_t* steps_host);
 /* The three standard normals the Euler move of step `step` draws for bead
  * `bead` of the chain with global id `chain_id`, computed on the device in
  * the handle's precision: out_dev [count][3] FP64 for beads bead..bead+count-1.
- * Streams (Philox4x32-10, key = seed, counter = (index | purpose << 16,
- * chain id, k), k = step >> 1): steps 2k and 2k+1 share the Box-Muller
+ * Streams (Philox4x32-10, key = seed, counter = (index, chain id, k lo,
+ * k hi | purpose << 24), k = step >> 1): steps 2k and 2k+1 share the Box-Muller
  * normals (a0..a5) of blocks NOISE (a0..a3) and NOISE2 (a4, a5); step 2k
  * takes (a0, a1, a2), step 2k+1 takes (a3, a4, a5).  Used to test the random
  * streams in isolation. */

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ssp_oracle.c")
 _LIB = os.path.join(_HERE, "libssp_oracle.so")
 
-# Philox counter purposes (index | purpose << 16 in the first counter word).
+# Philox counter purposes (step hi | purpose << 24 in the last counter word).
 P_INIT_BOND, P_INIT_Z, P_INIT_S, P_INIT_ANCHOR, P_NOISE, P_SLOT, P_ANCHOR, P_NOISE2 = 1, 2, 3, 4, 5, 6, 7, 8
 
 # Event bits reported per slot by a single step.

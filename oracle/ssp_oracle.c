@@ -40,9 +40,9 @@
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11,
  * "Parallel random numbers: as easy as 1, 2, 3"), implemented here from the
  * published round function.  key = (seed_lo, seed_hi); counter =
- * (index | purpose << 16, chain_id, step_lo, step_hi).  A 32-bit word w maps
- * to u = ((w >> 9) + 0.5) * 2^-23 in (0,1); normals come from the
- * Box-Muller transform r = sqrt(-2 ln u_a), theta = 2 pi u_b,
+ * (index, chain_id, step_lo, step_hi | purpose << 24), steps below 2^56.
+ * A 32-bit word w maps to u = ((w >> 9) + 0.5) * 2^-23 in (0,1); normals
+ * come from the Box-Muller transform r = sqrt(-2 ln u_a), theta = 2 pi u_b,
  * (r cos theta, r sin theta).  Three normals per block: the pair from
  * (w0,w1) and the cosine member of the pair from (w2,w3).
  *
@@ -112,10 +112,10 @@ void ssp_oracle_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 static void draw(uint64_t seed, int purpose, int index, int64_t chain, int64_t step, uint32_t w[4])
 {
     uint32_t ctr[4], key[2];
-    ctr[0] = (uint32_t)index | ((uint32_t)purpose << 16);
+    ctr[0] = (uint32_t)index;
     ctr[1] = (uint32_t)chain;
     ctr[2] = (uint32_t)((uint64_t)step & 0xffffffffu);
-    ctr[3] = (uint32_t)((uint64_t)step >> 32);
+    ctr[3] = (uint32_t)((uint64_t)step >> 32) | ((uint32_t)purpose << 24);
     key[0] = (uint32_t)(seed & 0xffffffffu);
     key[1] = (uint32_t)(seed >> 32);
     ssp_oracle_philox(ctr, key, w);

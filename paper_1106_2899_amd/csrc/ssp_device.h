@@ -30,10 +30,14 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
+// Counter (index, chain id, step lo, step hi | purpose << 24), for steps below
+// 2^56.  The first round multiplies only the index and the step's low word,
+// so its two products are the same for every purpose at a given step and
+// index: a step's draws share them.
 __device__ __forceinline__ uint4 draw(uint32_t purpose, uint32_t index, uint32_t gid, int64_t step, uint32_t k0,
                                       uint32_t k1)
 {
-    return philox(make_uint4(index | (purpose << 16), gid, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32)),
+    return philox(make_uint4(index, gid, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32) | (purpose << 24)),
                   k0, k1);
 }
 

@@ -20,7 +20,7 @@ constexpr int kMaxCorrLevels = 16;
 enum CtrlWord { kCtrlSteps = 0, kCtrlCorrSamples = 1, kCtrlSeriesSamples = 2, kCtrlWords = 8 };
 enum FlagBits { kFlagNonFinite = 1u, kFlagSeriesOverflow = 2u, kFlagInternal = 4u };
 
-// Random-stream purposes (first counter word = index | purpose << 16).
+// Random-stream purposes (last counter word = step hi | purpose << 24).
 enum Purpose : uint32_t {
     kInitBond = 1,
     kInitZ = 2,
