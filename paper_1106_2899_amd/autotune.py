@@ -4,9 +4,10 @@ Chains are bucketed by length into the classes (2..8], (8..16], (16..32],
 (32..64], (64..128].  For every class present in an ensemble the tuner times
 each supported mapping (W lanes per chain, B beads per lane, W*B >= the
 longest chain of the class) on a probe ensemble made of a sample of that
-class's chains, using the library's kernel timing mode (HIP events around the
-step-kernel launches), and applies the fastest mapping.  Trajectories do not
-depend on the mapping, so tuning never changes results.
+class's chains, sampled at the ensemble's own stress interval, using the
+library's kernel timing mode (HIP events around the step-kernel launches),
+and applies the fastest mapping.  Trajectories do not depend on the mapping,
+so tuning never changes results.
 """
 from __future__ import annotations
 
@@ -38,11 +39,12 @@ class TuneResult:
         })
 
 
-def _time_mapping(lengths: np.ndarray, mapping, precision: str, steps: int, seed: int, kappa, device) -> float:
+def _time_mapping(lengths: np.ndarray, mapping, precision: str, steps: int, seed: int, kappa, device,
+                  sample_every: int = 1) -> float:
     from .ensemble import Ensemble
 
     lo, hi = int(lengths.min()), int(lengths.max())
-    e = Ensemble(lengths, precision=precision, seed=seed, corr_levels=0, use_graph=False,
+    e = Ensemble(lengths, precision=precision, seed=seed, corr_levels=0, use_graph=False, sample_every=sample_every,
                  max_steps_per_launch=steps, device=device)
     try:
         e.set_mapping(lo, hi, mapping[0], mapping[1])
@@ -82,7 +84,7 @@ def tune(ensemble, *, steps: int = 200, probe_chains: int = 16384, seed: int = 1
             times = {}
             for m in candidates(int(sel.max())):
                 times[m] = _time_mapping(np.ascontiguousarray(probe, dtype=np.int32), m, ensemble.precision, steps,
-                                         seed, None, ensemble.device)
+                                         seed, None, ensemble.device, ensemble.sample_every)
             res.timings[(lo, hi)] = times
             best = min(times, key=times.get)
             cached[ckey] = list(best)
