@@ -57,14 +57,22 @@ def algorithmic_valu_slots(sample_every: int = SAMPLE_EVERY, n0: float = 4.0) ->
     return 50.0 + 22.5 + 9.0 + 21.0 + 3.0 / n0 + 36.0 / n0 + 2.0 + 9.0 / n0 + (9.0 + 9.0 / n0) / sample_every
 
 
-def _sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+# The step kernel's source and the headers it is compiled with.
+KERNEL_SOURCES = ("ssp_step.hip", "ssp_device.h", "ssp_internal.h")
 
 
-def _traffic_from_profiles(kernel_src):
+def kernel_sources_sha():
+    """sha256 over the step kernel's source files, concatenated in order."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1106_2899_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _traffic_from_profiles():
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on a different kernel source."""
+    None when absent or taken on different kernel sources."""
     p = os.path.join(ROOT, "profiles", "step_kernel_lve_16384x32_counters.md")
     if not os.path.exists(p):
         return None
@@ -72,9 +80,9 @@ def _traffic_from_profiles(kernel_src):
     with open(p) as f:
         for line in f:
             k, _, v = line.strip().partition(": ")
-            if k in ("kernel_source_sha256", "hbm_bytes_per_launch"):
+            if k in ("kernel_sources_sha256", "hbm_bytes_per_launch"):
                 d[k] = v.strip()
-    if d.get("kernel_source_sha256") != _sha(kernel_src) or "hbm_bytes_per_launch" not in d:
+    if d.get("kernel_sources_sha256") != kernel_sources_sha() or "hbm_bytes_per_launch" not in d:
         return None
     return float(d["hbm_bytes_per_launch"])
 
@@ -200,7 +208,6 @@ def main():
     per_launch_s = ms / 1e3 / launches
     slots = algorithmic_valu_slots()
     achieved = slots * (bead_steps / launches) / per_launch_s
-    kernel_src = os.path.join(ROOT, "paper_1106_2899_amd", "csrc", "ssp_step.hip")
     roofline = {
         "bound": "alu",
         "kernel": "k_step<float,32,1,false>",
@@ -208,7 +215,7 @@ def main():
         "peak": PEAK_LANE_SLOTS,
         "unit": "VALU lane-slots/s",
         "frac": achieved / PEAK_LANE_SLOTS,
-        "traffic": _traffic_from_profiles(kernel_src),
+        "traffic": _traffic_from_profiles(),
         "algorithmic_slots_per_bead_step": slots,
         "launch_ms": per_launch_s * 1e3,
         "bead_steps_per_launch": bead_steps / launches,
