@@ -102,18 +102,24 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     T kap[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
-    const T* traj = reinterpret_cast<const T*>(a.traj);
+    using T4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
+    using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    const T4* traj = reinterpret_cast<const T4*>(a.traj);
+    const T2* traj2 = reinterpret_cast<const T2*>(a.traj2);
     T* lam = reinterpret_cast<T*>(a.lam);
     const int ca = (a.comp < 3) ? a.comp : (a.comp == 3 ? 0 : (a.comp == 4 ? 1 : 2));
     const int cb = (a.comp < 3) ? a.comp : (a.comp == 3 ? 1 : (a.comp == 4 ? 2 : 0));
 
     auto traj_r = [&](int row, int i) -> v3<T> {
-        const T* p = traj + ((int64_t)row * a.total + off + i) * 6;
-        return {p[0], p[1], p[2]};
+        const T4 p = traj[(int64_t)row * a.total + off + i];
+        return {p.x, p.y, p.z};
     };
-    auto traj_a = [&](int row, int i) -> v3<T> {
-        const T* p = traj + ((int64_t)row * a.total + off + i) * 6;
-        return {p[3], p[4], p[5]};
+    auto traj_ra = [&](int row, int i, v3<T>& R, v3<T>& A) {
+        const int64_t e = (int64_t)row * a.total + off + i;
+        const T4 p = traj[e];
+        const T2 q = traj2[e];
+        R = {p.x, p.y, p.z};
+        A = {p.w, q.x, q.y};
     };
 
     v3<T> lR[B], lA[B];
@@ -156,6 +162,32 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     for (int q = 0; q < 9; ++q) G[q] = 0.0;
     double Gns = 0.0;
 
+    // Step m reads the slot rows m and m + 1 and the trajectory row m.  Row
+    // m + 1 of the slots is row m of the step after, carried; row m and the
+    // trajectory are loaded one step ahead, so that their latency runs under
+    // the previous step's arithmetic.
+    int s_next[B], s_pre[B];
+    v3<T> R_pre[B], A_pre[B];
+    auto prefetch = [&](int m) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = li * B + b;
+            s_pre[b] = -1;
+            R_pre[b] = zero3<T>();
+            A_pre[b] = zero3<T>();
+            if (i < n) {
+                s_pre[b] = (int)a.rec_s[(a.m0 + m) * a.total + off + i];
+                traj_ra(m, i, R_pre[b], A_pre[b]);
+            }
+        }
+    };
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = li * B + b;
+        s_next[b] = (i < n) ? (int)a.rec_s[(a.m0 + a.len) * a.total + off + i] : -1;
+    }
+    if (a.len > 0) prefetch(a.len - 1);
+
     for (int m = a.len - 1; m >= 0; --m) {
         const int64_t mg = a.m0 + m;
         int sm[B], s1[B];
@@ -164,15 +196,15 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         bool cr[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int i = li * B + b;
-            const bool act = i < n;
-            sm[b] = act ? (int)a.rec_s[mg * a.total + off + i] : -1;
-            s1[b] = act ? (int)a.rec_s[(mg + 1) * a.total + off + i] : -1;
-            Rm[b] = act ? traj_r(m, i) : zero3<T>();
-            Am[b] = act ? traj_a(m, i) : zero3<T>();
+            sm[b] = s_pre[b];
+            s1[b] = s_next[b];
+            s_next[b] = sm[b];
+            Rm[b] = R_pre[b];
+            Am[b] = A_pre[b];
             cr[b] = sm[b] < 0 && s1[b] >= 0;
             any_cr |= cr[b];
         }
+        if (m > 0) prefetch(m - 1);
         // created springs: their anchor depends on the end bead after the move
         if (__ballot(any_cr) != 0) {
 #pragma unroll

@@ -761,7 +761,7 @@ namespace {
 // Regions of a recording buffer: slot rows, checkpoints, replay state and
 // control words, segment trajectory, carried adjoint.
 struct RecLayout {
-    size_t rows, ckpts, scratch, ctrl, traj, lam, total;
+    size_t rows, ckpts, scratch, ctrl, traj, traj2, lam, total;
     int n_seg;
 };
 
@@ -781,7 +781,8 @@ RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
     L.ckpts = take((size_t)L.n_seg * h->lay.state_total);
     L.scratch = take(h->lay.state_total);
     L.ctrl = take(sizeof(int64_t) * kCtrlWords);
-    L.traj = take((size_t)(ckpt + 1) * beads * 6 * t);
+    L.traj = take((size_t)(ckpt + 1) * beads * 4 * t);
+    L.traj2 = take((size_t)(ckpt + 1) * beads * 2 * t);
     L.lam = take(beads * 6 * t);
     L.total = o;
     return L;
@@ -881,6 +882,7 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.flags = h->flags();
             a.total = h->res.total_beads;
             a.traj = rec + R.traj;
+            a.traj2 = rec + R.traj2;
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
         }
         for (auto& g : h->groups) {
@@ -895,6 +897,7 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.m0 = (int64_t)c * h->rec.ckpt;
             a.len = (int32_t)m;
             a.traj = rec + R.traj;
+            a.traj2 = rec + R.traj2;
             a.lam = rec + R.lam;
             a.grad = grad_dev;
             a.total = h->res.total_beads;

@@ -74,7 +74,10 @@ struct StepArgs {
     int8_t* rec_s;         // [window+1][total]: slot state after step g stored at row g + 1 - rec_g0
     int64_t rec_g0;
     int64_t total;         // beads (= slots) in the ensemble
-    void* traj;            // [n_steps+1][total][6] T: (R, A) at launch start and after every step
+    // (R, A) at launch start and after every step, in two planes of vectors
+    // so that one lane stores each with one instruction:
+    void* traj;            // [n_steps+1][total] T4: (R.x, R.y, R.z, A.x)
+    void* traj2;           // [n_steps+1][total] T2: (A.y, A.z)
 };
 
 struct AdjointArgs {
@@ -87,7 +90,8 @@ struct AdjointArgs {
     int64_t rec_g0;         // global step index of the window start
     int64_t m0;             // window index of the segment start
     int32_t len;            // steps in the segment
-    const void* traj;       // [len+1][total][6] T
+    const void* traj;       // [len+1][total] T4: (R.x, R.y, R.z, A.x)
+    const void* traj2;      // [len+1][total] T2: (A.y, A.z)
     void* lam;              // [total][6] T: dJ/dR, dJ/dA carried between segments
     double* grad;           // [M][10]: dJ/dkappa (row-major), dJ/dN_s (accumulated)
     int64_t total;

@@ -253,18 +253,23 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     // Trajectory rows for the adjoint replay: (R, A) of every bead/slot, with
     // FP32 positions rounded from hi + lo.
     auto store_traj = [&](int row) {
-        T* tr = reinterpret_cast<T*>(a.traj) + ((int64_t)row * a.total + off) * 6;
+        using T4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
+        using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+        const int64_t e = (int64_t)row * a.total + off;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
             if (i < n) {
-                T* p = tr + (int64_t)i * 6;
-                p[0] = rh[b].x + rl[b].x;
-                p[1] = rh[b].y + rl[b].y;
-                p[2] = rh[b].z + rl[b].z;
-                p[3] = ah[b].x + al[b].x;
-                p[4] = ah[b].y + al[b].y;
-                p[5] = ah[b].z + al[b].z;
+                T4 p;
+                p.x = rh[b].x + rl[b].x;
+                p.y = rh[b].y + rl[b].y;
+                p.z = rh[b].z + rl[b].z;
+                p.w = ah[b].x + al[b].x;
+                T2 q;
+                q.x = ah[b].y + al[b].y;
+                q.y = ah[b].z + al[b].z;
+                reinterpret_cast<T4*>(a.traj)[e + i] = p;
+                reinterpret_cast<T2*>(a.traj2)[e + i] = q;
             }
         }
     };

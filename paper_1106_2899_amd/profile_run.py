@@ -2,6 +2,7 @@
 
     python -m paper_1106_2899_amd.profile_run step   # step kernel, 16384 x N=32, 3 launches of 5000 steps
     python -m paper_1106_2899_amd.profile_run copy   # 1 GiB read + 1 GiB write elementwise copy (counter calibration)
+    python -m paper_1106_2899_amd.profile_run adjoint  # 65536 x N=64 under shear 0.01: forward, recorded forward, reverse
 """
 from __future__ import annotations
 
@@ -22,6 +23,21 @@ def step(launches: int = 3, md_steps: int = 5000) -> None:
     print("step launches:", launches, "bead-steps per launch:", 16384 * 32 * md_steps, flush=True)
 
 
+def adjoint(chains: int = 65536, beads: int = 64, window: int = 2000, ckpt: int = 100, rate: float = 0.01) -> None:
+    from .ensemble import Ensemble
+
+    kap = torch.zeros(1, 9, dtype=torch.float64, device="cuda")
+    kap[0, 1] = rate
+    e = Ensemble(beads, chains, precision="fp32", seed=5, sample_every=10, corr_levels=0, use_graph=False)
+    e.init()
+    e.step(window, kap)
+    e.forward_record(window, ckpt, kap)
+    g = e.adjoint()
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all()
+    print("adjoint window:", window, "checkpoint every:", ckpt, "bead-steps per pass:", chains * beads * window, flush=True)
+
+
 def copy(nbytes: int = 1 << 30) -> None:
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -32,4 +48,4 @@ def copy(nbytes: int = 1 << 30) -> None:
 
 
 if __name__ == "__main__":
-    {"step": step, "copy": copy}[sys.argv[1]]()
+    {"step": step, "copy": copy, "adjoint": adjoint}[sys.argv[1]]()
