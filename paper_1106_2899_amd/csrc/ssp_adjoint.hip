@@ -102,25 +102,44 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     T kap[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
-    using T4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
-    using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
-    const T4* traj = reinterpret_cast<const T4*>(a.traj);
-    const T2* traj2 = reinterpret_cast<const T2*>(a.traj2);
+    const v3<T>* trajR = reinterpret_cast<const v3<T>*>(a.traj);
+    const v3<T>* trajA = reinterpret_cast<const v3<T>*>(a.traj2);
     T* lam = reinterpret_cast<T*>(a.lam);
+
+    // Anchors run backwards: a spring that survives step m was only advected,
+    // A_{m+1} = (I + K) A_m with K = dt kappa as the step kernel rounds it, so
+    // A_m = A_{m+1} + D A_{m+1}, D = (I + K)^{-1} - I = -(I + K)^{-1} K.  D is
+    // O(dt kappa), so D A in T costs no precision; A itself is carried in
+    // FP64.  Anchors of destroyed springs and those at the segment end are
+    // read from the replay output.
+    T dinv[9];
+    {
+        double K[9], M[9], Mi[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            K[q] = valid ? (double)T(a.ph.dt * a.kappa[9 * elem + q]) : 0.0;
+            M[q] = K[q] + ((q % 4 == 0) ? 1.0 : 0.0);
+        }
+        Mi[0] = M[4] * M[8] - M[5] * M[7];
+        Mi[1] = M[2] * M[7] - M[1] * M[8];
+        Mi[2] = M[1] * M[5] - M[2] * M[4];
+        Mi[3] = M[5] * M[6] - M[3] * M[8];
+        Mi[4] = M[0] * M[8] - M[2] * M[6];
+        Mi[5] = M[2] * M[3] - M[0] * M[5];
+        Mi[6] = M[3] * M[7] - M[4] * M[6];
+        Mi[7] = M[1] * M[6] - M[0] * M[7];
+        Mi[8] = M[0] * M[4] - M[1] * M[3];
+        const double det = M[0] * Mi[0] + M[1] * Mi[3] + M[2] * Mi[6];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                dinv[3 * r + c] = T(-(Mi[3 * r] * K[c] + Mi[3 * r + 1] * K[3 + c] + Mi[3 * r + 2] * K[6 + c]) / det);
+    }
     const int ca = (a.comp < 3) ? a.comp : (a.comp == 3 ? 0 : (a.comp == 4 ? 1 : 2));
     const int cb = (a.comp < 3) ? a.comp : (a.comp == 3 ? 1 : (a.comp == 4 ? 2 : 0));
 
-    auto traj_r = [&](int row, int i) -> v3<T> {
-        const T4 p = traj[(int64_t)row * a.total + off + i];
-        return {p.x, p.y, p.z};
-    };
-    auto traj_ra = [&](int row, int i, v3<T>& R, v3<T>& A) {
-        const int64_t e = (int64_t)row * a.total + off + i;
-        const T4 p = traj[e];
-        const T2 q = traj2[e];
-        R = {p.x, p.y, p.z};
-        A = {p.w, q.x, q.y};
-    };
+    auto traj_r = [&](int row, int i) -> v3<T> { return trajR[(int64_t)row * a.total + off + i]; };
 
     v3<T> lR[B], lA[B];
     if (a.seed_lambda) {
@@ -167,24 +186,29 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     // trajectory are loaded one step ahead, so that their latency runs under
     // the previous step's arithmetic.
     int s_next[B], s_pre[B];
-    v3<T> R_pre[B], A_pre[B];
+    v3<T> R_pre[B];
     auto prefetch = [&](int m) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
             s_pre[b] = -1;
             R_pre[b] = zero3<T>();
-            A_pre[b] = zero3<T>();
             if (i < n) {
                 s_pre[b] = (int)a.rec_s[(a.m0 + m) * a.total + off + i];
-                traj_ra(m, i, R_pre[b], A_pre[b]);
+                R_pre[b] = traj_r(m, i);
             }
         }
     };
+    v3<double> Ac[B];  // A_{m+1} of the springs alive after step m
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int i = li * B + b;
         s_next[b] = (i < n) ? (int)a.rec_s[(a.m0 + a.len) * a.total + off + i] : -1;
+        Ac[b] = {0.0, 0.0, 0.0};
+        if (i < n) {
+            const v3<T> v = trajA[(int64_t)a.len * a.total + off + i];
+            Ac[b] = {(double)v.x, (double)v.y, (double)v.z};
+        }
     }
     if (a.len > 0) prefetch(a.len - 1);
 
@@ -200,9 +224,21 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             s1[b] = s_next[b];
             s_next[b] = sm[b];
             Rm[b] = R_pre[b];
-            Am[b] = A_pre[b];
             cr[b] = sm[b] < 0 && s1[b] >= 0;
             any_cr |= cr[b];
+            Am[b] = zero3<T>();
+            if (sm[b] >= 0) {
+                v3<double> Ap = Ac[b];
+                if (s1[b] < 0) {  // destroyed in step m: its advected anchor was written at row m + 1
+                    const v3<T> v = trajA[(int64_t)(m + 1) * a.total + off + li * B + b];
+                    Ap = {(double)v.x, (double)v.y, (double)v.z};
+                }
+                const v3<T> At = {T(Ap.x), T(Ap.y), T(Ap.z)};
+                Ac[b] = {Ap.x + (double)(dinv[0] * At.x + dinv[1] * At.y + dinv[2] * At.z),
+                         Ap.y + (double)(dinv[3] * At.x + dinv[4] * At.y + dinv[5] * At.z),
+                         Ap.z + (double)(dinv[6] * At.x + dinv[7] * At.y + dinv[8] * At.z)};
+                Am[b] = {T(Ac[b].x), T(Ac[b].y), T(Ac[b].z)};
+            }
         }
         if (m > 0) prefetch(m - 1);
         // created springs: their anchor depends on the end bead after the move

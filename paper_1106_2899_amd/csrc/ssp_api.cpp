@@ -781,8 +781,8 @@ RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
     L.ckpts = take((size_t)L.n_seg * h->lay.state_total);
     L.scratch = take(h->lay.state_total);
     L.ctrl = take(sizeof(int64_t) * kCtrlWords);
-    L.traj = take((size_t)(ckpt + 1) * beads * 4 * t);
-    L.traj2 = take((size_t)(ckpt + 1) * beads * 2 * t);
+    L.traj = take((size_t)(ckpt + 1) * beads * 3 * t);
+    L.traj2 = take((size_t)(ckpt + 1) * beads * 3 * t);
     L.lam = take(beads * 6 * t);
     L.total = o;
     return L;
@@ -883,6 +883,8 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.total = h->res.total_beads;
             a.traj = rec + R.traj;
             a.traj2 = rec + R.traj2;
+            a.replay_s = rows;  // the recorded slot states, replayed
+            a.rec_g0 = h->rec.g0;
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
         }
         for (auto& g : h->groups) {

@@ -73,11 +73,12 @@ struct StepArgs {
     // adjoint support (all optional)
     int8_t* rec_s;         // [window+1][total]: slot state after step g stored at row g + 1 - rec_g0
     int64_t rec_g0;
+    const int8_t* replay_s;  // [window+1][total], rows as rec_s: replay these slot states instead of deciding them
     int64_t total;         // beads (= slots) in the ensemble
-    // (R, A) at launch start and after every step, in two planes of vectors
-    // so that one lane stores each with one instruction:
-    void* traj;            // [n_steps+1][total] T4: (R.x, R.y, R.z, A.x)
-    void* traj2;           // [n_steps+1][total] T2: (A.y, A.z)
+    // Replay output (with replay_s), rows 0..n_steps of the launch:
+    void* traj;            // [n_steps+1][total] T3: R at launch start and after every step
+    void* traj2;           // [n_steps+1][total] T3: A of every slot at row n_steps; at row m + 1 the
+                           // anchor of each spring destroyed in step m (as advected by that step); nothing else
 };
 
 struct AdjointArgs {
@@ -90,8 +91,8 @@ struct AdjointArgs {
     int64_t rec_g0;         // global step index of the window start
     int64_t m0;             // window index of the segment start
     int32_t len;            // steps in the segment
-    const void* traj;       // [len+1][total] T4: (R.x, R.y, R.z, A.x)
-    const void* traj2;      // [len+1][total] T2: (A.y, A.z)
+    const void* traj;       // [len+1][total] T3: R (replay output)
+    const void* traj2;      // [len+1][total] T3: A at row len and of the springs destroyed in each step (replay output)
     void* lam;              // [total][6] T: dJ/dR, dJ/dA carried between segments
     double* grad;           // [M][10]: dJ/dkappa (row-major), dJ/dN_s (accumulated)
     int64_t total;

@@ -126,11 +126,14 @@ template <typename T, int B> struct WaveLds {
     uint32_t first[kWaveSize * B];
 };
 
-// K1: construction by the K = 1 rule (one attempt per chain and step, by the
-// lowest empty slot) instead of K = C - Z; a template parameter so that
-// neither kernel carries the other rule's work.
-template <typename T, int W, int B, bool K1>
-__global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
+// The step, for the kernels below.  K1: construction by the K = 1 rule (one
+// attempt per chain and step, by the lowest empty slot) instead of K = C - Z;
+// a template parameter so that neither kernel carries the other rule's work.
+// RP: replay of a recorded run: the slot state after each step is read from
+// the recorded rows instead of being decided (no hop or construction draws or
+// probabilities); positions and anchors follow bit for bit.
+template <typename T, int W, int B, bool K1, bool RP>
+__device__ __forceinline__ void step_body(const StepArgs& a)
 {
     constexpr bool kComp = std::is_same<T, float>::value;  // (hi, lo) position sums
     constexpr int kChainsPerWave = kWaveSize / W;
@@ -252,28 +255,22 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 
     // Trajectory rows for the adjoint replay: (R, A) of every bead/slot, with
     // FP32 positions rounded from hi + lo.
-    auto store_traj = [&](int row) {
-        using T4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
-        using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    // Replay output: R after every step (row 0: launch start).  Anchors are
+    // written only where the adjoint cannot recover them by running the
+    // advection backwards: for every slot at the launch end, and for each
+    // spring destroyed in a step, at that step's row.
+    auto store_r = [&](int row) {
         const int64_t e = (int64_t)row * a.total + off;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
-            if (i < n) {
-                T4 p;
-                p.x = rh[b].x + rl[b].x;
-                p.y = rh[b].y + rl[b].y;
-                p.z = rh[b].z + rl[b].z;
-                p.w = ah[b].x + al[b].x;
-                T2 q;
-                q.x = ah[b].y + al[b].y;
-                q.y = ah[b].z + al[b].z;
-                reinterpret_cast<T4*>(a.traj)[e + i] = p;
-                reinterpret_cast<T2*>(a.traj2)[e + i] = q;
-            }
+            if (i < n) reinterpret_cast<v3<T>*>(a.traj)[e + i] = rh[b] + rl[b];
         }
     };
-    if (a.traj) store_traj(0);
+    auto store_a = [&](int row, int b) {
+        reinterpret_cast<v3<T>*>(a.traj2)[(int64_t)row * a.total + off + li * B + b] = ah[b] + al[b];
+    };
+    if constexpr (RP) store_r(0);
 
     const int64_t g0 = a.ctrl[kCtrlSteps];
     bool finite_ok = true;
@@ -306,8 +303,27 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
     int phase = a.sample_every > 0 ? (int)((g0 + 1) % a.sample_every) : 1;
     int64_t q_launch = 0;  // samples already written by this launch
 
+    // Replay: the recorded slot row of a step is loaded one step ahead, so that
+    // its latency runs under the previous step.
+    int replay_next[B], replay_ahead[B];
+    auto replay_load = [&](int64_t gs, int (&dst)[B]) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = li * B + b;
+            dst[b] = (j < n) ? (int)a.replay_s[(gs + 1 - a.rec_g0) * a.total + off + j] : -1;
+        }
+    };
+    if constexpr (RP) {
+        if (a.n_steps > 0) replay_load(g0, replay_ahead);
+    }
+
     for (int step = 0; step < a.n_steps; ++step) {
         const int64_t g = g0 + step;
+        if constexpr (RP) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) replay_next[b] = replay_ahead[b];
+            if (step + 1 < a.n_steps) replay_load(g + 1, replay_ahead);
+        }
         const bool even = (g & 1) == 0;  // wave-uniform
         const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
 
@@ -423,8 +439,32 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
 
         // ---- substep 2: hops from the post-move positions.
         uint32_t wrec[B];  // reconstruction words
+        int s_rec[B];      // replay: the recorded slot state after this step
+        if constexpr (RP) {
+            bool bad = false;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
+            for (int b = 0; b < B; ++b) {
+                const int j = li * B + b;
+                s_rec[b] = -1;
+                wrec[b] = 0u;
+                if (even) {  // the pair's carried normals still come from NOISE2
+                    const uint4 y = draw(kNoise2, (uint32_t)j, gid, kp, k0, k1);
+                    carry_w0[b] = y.x;
+                    carry_w1[b] = y.y;
+                }
+                if (j < n) {
+                    const int v = replay_next[b];
+                    // a creation lands on an end; anything else moves by at most one bead
+                    const bool ok = s[b] >= 0 ? (v == -1 || (v >= s[b] - 1 && v <= s[b] + 1 && v < n))
+                                              : (v == -1 || v == 0 || v == n - 1);
+                    bad |= !ok;
+                    s_rec[b] = ok ? v : s[b];
+                }
+            }
+            if (bad) atomicOr(a.flags, kFlagInternal);
+        }
+#pragma unroll
+        for (int b = 0; b < B && !RP; ++b) {
             const int j = li * B + b;
             uint32_t whop;
             if (even) {
@@ -465,7 +505,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         int z = 0;
         int first_empty = kCap;  // lowest empty slot of the chain (K = 1 rule)
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
+        for (int b = 0; b < B && !RP; ++b) {
             z += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
             if constexpr (K1) {
                 const uint64_t m = __ballot(s[b] < 0 && li * B + b < n) & seg_mask<W>(sb);
@@ -476,13 +516,22 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
         const uint32_t t1 = thr[K < 0 ? 0 : K];
         const uint32_t t2 = thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
         int create_at[B];
+        bool destroyed[B];
         bool any_create = false;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = li * B + b;
             const uint32_t uw = wrec[b] >> 9;
             create_at[b] = -1;
-            if (j < n) {
+            destroyed[b] = false;
+            if constexpr (RP) {
+                if (s[b] < 0) {
+                    create_at[b] = s_rec[b];
+                } else {
+                    destroyed[b] = s_rec[b] < 0;
+                    s[b] = s_rec[b];
+                }
+            } else if (j < n) {
                 if (s[b] >= 0) {
                     if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) s[b] = -1;
                 } else if (!K1 || j == first_empty) {
@@ -522,7 +571,12 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             for (int b = 0; b < B; ++b)
                 if (li * B + b < n) row[li * B + b] = (int8_t)s[b];
         }
-        if (a.traj) store_traj(step + 1);
+        if constexpr (RP) {
+            store_r(step + 1);
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (destroyed[b]) store_a(step + 1, b);
+        }
 
         // ---- observables of the new state.
         if (a.sample_every > 0 && phase == 0) {
@@ -583,7 +637,26 @@ __global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
             a.st.s[off + i] = s[b];
         }
     }
+    if constexpr (RP) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (li * B + b < n) store_a(a.n_steps, b);
+    }
     if (!finite_ok) atomicOr(a.flags, kFlagNonFinite);
+}
+
+template <typename T, int W, int B, bool K1>
+__global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
+{
+    step_body<T, W, B, K1, false>(a);
+}
+
+// Replay of recorded slot rows (the adjoint's reverse pass re-creates each
+// segment's trajectory this way).
+template <typename T, int W, int B>
+__global__ void __launch_bounds__(kGroupThreads) k_replay(StepArgs a)
+{
+    step_body<T, W, B, false, true>(a);
 }
 
 template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipStream_t s)
@@ -591,7 +664,9 @@ template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipSt
     constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
     const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
     if (groups == 0) return hipSuccess;
-    if (a.construct_rule == 1)
+    if (a.replay_s)
+        hipLaunchKernelGGL((k_replay<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    else if (a.construct_rule == 1)
         hipLaunchKernelGGL((k_step<T, W, B, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     else
         hipLaunchKernelGGL((k_step<T, W, B, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
