@@ -241,7 +241,11 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
  * J_k = sigma_component of chain k at the end of the window (component 0..5
  * = xx yy zz xy yz zx).  kappa_dev must hold the velocity gradient of the
  * recorded window.  init_window != 0 adds the N_s dependence of the sampled
- * initial anchors when the window started at step 0.  Synchronises. */
+ * initial anchors when the window started at step 0.  Synchronises.  Every
+ * recorded slot row is checked as it is read (a state the step could have
+ * produced from the one before); a recording changed since
+ * ssp_forward_record fails with SSP_EINVAL, leaves the ensemble's own state
+ * untouched and gives no valid gradients. */
 int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
                 double* grad_dev, ssp_stream stream);
 

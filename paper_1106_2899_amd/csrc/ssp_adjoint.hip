@@ -185,6 +185,16 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     // m + 1 of the slots is row m of the step after, carried; row m and the
     // trajectory are loaded one step ahead, so that their latency runs under
     // the previous step's arithmetic.
+    // Recorded slot rows are checked before use as LDS indices (where they are
+    // used, not where they are loaded, so that a prefetch is not waited for):
+    // a value outside -1..n-1 reads as an empty slot and latches kFlagReplay.
+    bool bad_row = false;
+    auto checked = [&](int v) -> int {
+        const bool ok = v >= -1 && v < n;
+        bad_row |= !ok;
+        return ok ? v : -1;
+    };
+    auto row_at = [&](int64_t r, int i) -> int { return checked(a.rec_s[r * a.total + off + i]); };
     int s_next[B], s_pre[B];
     v3<T> R_pre[B];
     auto prefetch = [&](int m) {
@@ -194,7 +204,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             s_pre[b] = -1;
             R_pre[b] = zero3<T>();
             if (i < n) {
-                s_pre[b] = (int)a.rec_s[(a.m0 + m) * a.total + off + i];
+                s_pre[b] = a.rec_s[(a.m0 + m) * a.total + off + i];  // checked when used
                 R_pre[b] = traj_r(m, i);
             }
         }
@@ -203,7 +213,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int i = li * B + b;
-        s_next[b] = (i < n) ? (int)a.rec_s[(a.m0 + a.len) * a.total + off + i] : -1;
+        s_next[b] = (i < n) ? row_at(a.m0 + a.len, i) : -1;
         Ac[b] = {0.0, 0.0, 0.0};
         if (i < n) {
             const v3<T> v = trajA[(int64_t)a.len * a.total + off + i];
@@ -220,7 +230,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         bool cr[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            sm[b] = s_pre[b];
+            sm[b] = checked(s_pre[b]);
             s1[b] = s_next[b];
             s_next[b] = sm[b];
             Rm[b] = R_pre[b];
@@ -351,7 +361,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = li * B + b;
-            const int s0 = (j < n) ? (int)a.rec_s[off + j] : -1;
+            const int s0 = (j < n) ? row_at(0, j) : -1;
             if (s0 >= 0) {
                 const v3<double> g = normals3_f64(draw(kInitAnchor, (uint32_t)j, gid, 0, a.ph.key0, a.ph.key1));
                 Gns += ((double)lA[b].x * g.x + (double)lA[b].y * g.y + (double)lA[b].z * g.z) * dsig;
@@ -372,6 +382,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             p[5] = lA[b].z;
         }
     }
+    if (bad_row) atomicOr(a.flags, kFlagReplay);
     // per-chain sums of the lane accumulators, in lane order
 #pragma unroll
     for (int q = 0; q < 9; ++q) sums[lane * 10 + q] = G[q];

@@ -906,8 +906,22 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.comp = component;
             a.seed_lambda = (c == R.n_seg - 1) ? 1 : 0;
             a.init_terms = (c == 0 && init_window && h->rec.g0 == 0) ? 1 : 0;
+            a.flags = h->flags();
             HIPCHK(h, launch_adjoint(k.precision, g.first.W, g.first.B, a, s));
         }
+    }
+    // A bad recording leaves the ensemble itself untouched (the replay runs on
+    // a scratch copy): report it and clear its flag.
+    uint32_t f = 0;
+    HIPCHK(h, hipMemcpyAsync(&f, h->flags(), sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (f & kFlagReplay) {
+        f &= ~(uint32_t)kFlagReplay;
+        HIPCHK(h, hipMemcpyAsync(h->flags(), &f, sizeof(f), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        return fail(h, SSP_EINVAL,
+                    "the recorded slot rows are not a run of this ensemble (recording buffer changed since "
+                    "ssp_forward_record, or recorded by another handle); gradients are invalid");
     }
     return check_flags(h, s);
 }

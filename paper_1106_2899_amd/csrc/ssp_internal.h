@@ -18,7 +18,7 @@ constexpr int kMaxCorrLevels = 16;
 // ctrl[] words in the work buffer (device-resident so that captured graphs
 // can be replayed at any step count).
 enum CtrlWord { kCtrlSteps = 0, kCtrlCorrSamples = 1, kCtrlSeriesSamples = 2, kCtrlWords = 8 };
-enum FlagBits { kFlagNonFinite = 1u, kFlagSeriesOverflow = 2u, kFlagInternal = 4u };
+enum FlagBits { kFlagNonFinite = 1u, kFlagSeriesOverflow = 2u, kFlagInternal = 4u, kFlagReplay = 8u };
 
 // Random-stream purposes (last counter word = step hi | purpose << 24).
 enum Purpose : uint32_t {
@@ -95,6 +95,7 @@ struct AdjointArgs {
     const void* traj2;      // [len+1][total] T3: A at row len and of the springs destroyed in each step (replay output)
     void* lam;              // [total][6] T: dJ/dR, dJ/dA carried between segments
     double* grad;           // [M][10]: dJ/dkappa (row-major), dJ/dN_s (accumulated)
+    uint32_t* flags;        // kFlagReplay: a recorded slot row out of range (read as empty)
     int64_t total;
     int32_t comp;           // objective component 0..5 (xx yy zz xy yz zx)
     int32_t seed_lambda;    // 1 for the last segment: start from dJ/dR at its end

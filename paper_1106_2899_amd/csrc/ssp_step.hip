@@ -461,7 +461,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
                     s_rec[b] = ok ? v : s[b];
                 }
             }
-            if (bad) atomicOr(a.flags, kFlagInternal);
+            if (bad) atomicOr(a.flags, kFlagReplay);
         }
 #pragma unroll
         for (int b = 0; b < B && !RP; ++b) {

@@ -98,3 +98,29 @@ def test_autograd_function_matches_adjoint_means():
     np.testing.assert_allclose(rates.grad.numpy(), w.numpy() * d_rate, rtol=1e-9)
     np.testing.assert_allclose(float(ns.grad), float((w.numpy() * d_ns).sum()), rtol=1e-9)
     np.testing.assert_allclose(J.detach().cpu().numpy(), o.stress()[:, 3].reshape(E, per).mean(axis=1), rtol=1e-10)
+
+
+def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble():
+    """A slot row changed after ssp_forward_record (an impossible state, 100 in
+    a chain of N = 8) is caught where the replay and the adjoint read it (both
+    kernels check a row before using it, and read a bad entry as an empty
+    slot): ssp_adjoint fails, the ensemble's own state is untouched, and a new
+    recording differentiates normally."""
+    from paper_1106_2899_amd._lib import SspError
+
+    N, M, T, ckpt = 8, 64, 40, 10
+    kap = _shear(0.1)
+    e = _ens(N, M, precision="fp32", seed=31, corr_levels=0).init()
+    e.forward_record(T, ckpt, kap)
+    before = [x.clone() for x in e.state()]
+    # slot rows: the first region of the recording buffer, [T + 1][N * M] int8
+    off = e._rec_p - e._rec_t.data_ptr()
+    rows = e._rec_t[off:off + (T + 1) * N * M].view(T + 1, N * M)
+    rows[20, 3] = 100
+    torch.cuda.synchronize()
+    with pytest.raises(SspError, match="recorded slot rows"):
+        e.adjoint(component=3)
+    assert all(torch.equal(x, y) for x, y in zip(before, e.state()))
+    e.forward_record(T, ckpt, kap)
+    g = e.adjoint(component=3)
+    assert torch.isfinite(g).all()
