@@ -4,7 +4,8 @@
 // final stress component J = sigma_c(R_T) of every chain with respect to the
 // velocity gradient kappa (all nine entries) and the slip-spring strength
 // N_s.  One launch processes one checkpoint segment backwards, reading the
-// (R, A) trajectory that the replay of the segment stored.
+// positions that the replay of the segment stored (k_replay) and rebuilding
+// the anchors from the few the replay stored.
 //
 // Per step m of the segment (state before the step: R_m, A_m, slots S_m;
 // after: S_{m+1}), with lR = dJ/dR_{m+1}, lA = dJ/dA_{m+1}:

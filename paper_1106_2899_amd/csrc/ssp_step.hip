@@ -27,6 +27,10 @@
 //      thresholds, identical in every precision),
 //   5. anchor offsets recomputed from the stored positions, and the stress /
 //      virtual stress of the new state every sample_every steps.
+//
+// k_replay is the same step with the slot decisions of 3 and 4 read from a
+// recording: the adjoint's reverse pass re-creates each checkpoint segment's
+// positions with it.
 #include <type_traits>
 
 #include "ssp_device.h"
@@ -253,12 +257,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     bonds_and_records();
     refresh_offsets();
 
-    // Trajectory rows for the adjoint replay: (R, A) of every bead/slot, with
-    // FP32 positions rounded from hi + lo.
-    // Replay output: R after every step (row 0: launch start).  Anchors are
-    // written only where the adjoint cannot recover them by running the
-    // advection backwards: for every slot at the launch end, and for each
-    // spring destroyed in a step, at that step's row.
+    // Replay output: R after every step (row 0: launch start), FP32 positions
+    // rounded from hi + lo.  Anchors are written only where the adjoint cannot
+    // recover them by running the advection backwards: for every slot at the
+    // launch end, and for each spring destroyed in a step, at that step's row.
     auto store_r = [&](int row) {
         const int64_t e = (int64_t)row * a.total + off;
 #pragma unroll

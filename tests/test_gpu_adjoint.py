@@ -124,3 +124,21 @@ def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble():
     e.forward_record(T, ckpt, kap)
     g = e.adjoint(component=3)
     assert torch.isfinite(g).all()
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_adjoint_under_the_k1_construction_rule(precision, rtol):
+    """The reverse pass replays recorded slot states, whatever rule decided
+    them: a window recorded under the K = 1 rule differentiates like the
+    oracle's run under the same rule."""
+    N, M, T, ckpt = 10, 24, 200, 48  # segments 48, 48, 48, 48, 8
+    kap = _shear(0.2)
+    e = _ens(N, M, precision=precision, seed=8, corr_levels=0, construct_rule=1).init()
+    e.forward_record(T, ckpt, kap)
+    got = e.adjoint(component=3).cpu().numpy()
+    o = oracle.Ensemble([N] * M, seed=8, construct_rule=1).init()
+    Rt, At, St = o.run_record(T, kap)
+    gk, gns = o.adjoint(Rt, At, St, kap, comp=3)
+    want = np.concatenate([gk.reshape(M, 9), gns[:, None]], axis=1)
+    assert np.array_equal(e.state()[2].cpu().numpy(), o.S)  # same events
+    _check(got, want, rtol)
