@@ -11,8 +11,9 @@ resident in HBM before the timed region.
 
 Printed: one JSON line with bead-steps/s of the batched FP32 path, the plain
 FP64 path at the same shape, the VALU roofline of the step kernel (measured
-with HIP events on the launch stream) and the FP64 CPU oracle timed on the
-host cores on a bounded sample.
+with HIP events on the launch stream), the adjoint/forward time ratio, the
+batched FP32 path on the start-up shear and polydisperse workloads (context),
+and the FP64 CPU oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -159,6 +160,44 @@ def adjoint_ratio(chains=65536, beads=64, window=2000, ckpt=100, rate=0.01, reps
     }
 
 
+def batched_configs(md_steps=1000, launches=3):
+    """Context, not the headline: bead-steps/s of the batched FP32 path on the
+    two flow workloads at their full sizes, timed over `launches` graph-replayed
+    calls of `md_steps` steps after one warm-up call (fewer steps than the
+    workloads' full runs; per-step work is the same).
+      startup_shear_4096x256x32: 1,048,576 chains of N = 32 in 4096 elements,
+        each sheared at its own rate, element series sampled every 10 steps;
+      polydisperse_2^18: 262,144 chains, N uniform in 16..128, shear or
+        uniaxial elongation per element, mapping chosen by the autotuner."""
+    import torch
+
+    from paper_1106_2899_amd import autotune, workloads
+    from paper_1106_2899_amd.ensemble import Ensemble
+
+    out = {}
+    for w, tune in ((workloads.startup_shear(), False), (workloads.polydisperse(), True)):
+        cap = (launches + 1) * md_steps // w.sample_every
+        e = Ensemble(w.n_beads, n_elements=w.n_elements, element_offsets=w.element_offsets, precision="fp32",
+                     seed=w.seed, sample_every=w.sample_every, corr_levels=0, series_capacity=cap,
+                     max_steps_per_launch=md_steps, use_graph=True)
+        if tune:
+            autotune.tune(e)
+        e.init()
+        kap = torch.as_tensor(w.kappa.reshape(w.n_elements, 9), dtype=torch.float64, device="cuda")
+        e.step(md_steps, kap)  # graph capture and warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(launches):
+            e.step(md_steps, kap)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert torch.isfinite(e.stress()).all()  # raises on a latched non-finite state
+        e.close()
+        out[w.name] = {"value": int(w.n_beads.sum()) * md_steps * launches / dt, "unit": "bead-steps/s",
+                       "steps": md_steps * launches}
+    return out
+
+
 def cpu_baseline(sample_chains=4096, sample_steps=16000):
     import oracle
 
@@ -246,6 +285,7 @@ def main():
         "fp32_over_fp64": v32 / v64,
         "roofline": roofline,
         "adjoint": adjoint_ratio(),
+        "batched_configs": batched_configs(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
