@@ -647,14 +647,25 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     if (!finite_ok) atomicOr(a.flags, kFlagNonFinite);
 }
 
+// Waves per SIMD the register budget must allow.  The one-bead FP32 step fits
+// 5 (96 VGPRs) by spilling a few values that only the sampling and the launch
+// epilogue use; at 4 waves (116 VGPRs, no spills) a 16384 x 32 launch is
+// 2.7 % slower and a 65536 x 64 one 8 % slower, because the fifth wave hides
+// more of the LDS round trips.  The other variants are left to the compiler.
+template <typename T, int B>
+constexpr int kStepWavesPerEu = (std::is_same<T, float>::value && B == 1) ? 5 : 1;
+
 template <typename T, int W, int B, bool K1>
-__global__ void __launch_bounds__(kGroupThreads) k_step(StepArgs a)
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>)))
+k_step(StepArgs a)
 {
     step_body<T, W, B, K1, false>(a);
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
-// segment's trajectory this way).
+// segment's trajectory this way).  No occupancy floor: at 5 waves its spills
+// fall inside the step loop (a segment of the 65536 x 64 adjoint took 3.4
+// instead of 2.9 ms).
 template <typename T, int W, int B>
 __global__ void __launch_bounds__(kGroupThreads) k_replay(StepArgs a)
 {
