@@ -581,35 +581,47 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         }
 
         // ---- observables of the new state.
-        if (a.sample_every > 0 && phase == 0) {
-            double p[kSampleValues];
-#pragma unroll
-            for (int q = 0; q < kSampleValues; ++q) p[q] = 0.0;
+        if (!RP && a.sample_every > 0 && phase == 0) {  // a replay samples nothing
             const double kss = 3.0 / a.ph.ns;
+            // Lane partials go to LDS in two groups of six as they are formed,
+            // so that the twelve FP64 sums are never live together (otherwise
+            // the sampling step sets the kernel's register peak).  Then a
+            // transpose: lane li of a segment sums values li, li + W, ... over
+            // the segment's lanes in lane order (deterministic).
+            double* mine = sums + lane * kSampleValues;
+            {
+                double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const double bx = br[b].x, by = br[b].y, bz = br[b].z;  // zero past the end
-                p[0] += 3.0 * bx * bx;
-                p[1] += 3.0 * by * by;
-                p[2] += 3.0 * bz * bz;
-                p[3] += 3.0 * bx * by;
-                p[4] += 3.0 * by * bz;
-                p[5] += 3.0 * bz * bx;
-                const double dx = d[b].x, dy = d[b].y, dz = d[b].z;  // zero when empty
-                p[6] += kss * dx * dx;
-                p[7] += kss * dy * dy;
-                p[8] += kss * dz * dz;
-                p[9] += kss * dx * dy;
-                p[10] += kss * dy * dz;
-                p[11] += kss * dz * dx;
+                for (int b = 0; b < B; ++b) {
+                    const double bx = br[b].x, by = br[b].y, bz = br[b].z;  // zero past the end
+                    p[0] += 3.0 * bx * bx;
+                    p[1] += 3.0 * by * by;
+                    p[2] += 3.0 * bz * bz;
+                    p[3] += 3.0 * bx * by;
+                    p[4] += 3.0 * by * bz;
+                    p[5] += 3.0 * bz * bx;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) mine[q] = p[q];
+            }
+            {
+                double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const double dx = d[b].x, dy = d[b].y, dz = d[b].z;  // zero when empty
+                    p[0] += kss * dx * dx;
+                    p[1] += kss * dy * dy;
+                    p[2] += kss * dz * dz;
+                    p[3] += kss * dx * dy;
+                    p[4] += kss * dy * dz;
+                    p[5] += kss * dz * dx;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) mine[6 + q] = p[q];
             }
             int z2 = 0;
 #pragma unroll
             for (int b = 0; b < B; ++b) z2 += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
-            // Transpose through LDS: lane li of a segment sums values li,
-            // li + W, ... over the segment's lanes in lane order (deterministic).
-#pragma unroll
-            for (int q = 0; q < kSampleValues; ++q) sums[lane * kSampleValues + q] = p[q];
             wave_sync();
 #pragma unroll
             for (int v = li; v < kSampleValues; v += W) {
@@ -663,9 +675,8 @@ k_step(StepArgs a)
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
-// segment's trajectory this way).  No occupancy floor: at 5 waves its spills
-// fall inside the step loop (a segment of the 65536 x 64 adjoint took 3.4
-// instead of 2.9 ms).
+// segment's trajectory this way).  It samples no stress, so without the
+// sampling code its registers fit 5 waves per SIMD with no spills.
 template <typename T, int W, int B>
 __global__ void __launch_bounds__(kGroupThreads) k_replay(StepArgs a)
 {
