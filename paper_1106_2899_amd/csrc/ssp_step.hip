@@ -659,13 +659,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     if (!finite_ok) atomicOr(a.flags, kFlagNonFinite);
 }
 
-// Waves per SIMD the register budget must allow.  The one-bead FP32 step fits
-// 5 (96 VGPRs) by spilling a few values that only the sampling and the launch
-// epilogue use; at 4 waves (116 VGPRs, no spills) a 16384 x 32 launch is
-// 2.7 % slower and a 65536 x 64 one 8 % slower, because the fifth wave hides
-// more of the LDS round trips.  The other variants are left to the compiler.
+// Waves per SIMD the register budget must allow.  The step is held one wave
+// above what its registers would give: FP32 with one bead per lane at 5 waves
+// (96 VGPRs instead of 106), with two at 4 (128 instead of 138), FP64 with
+// one at 3 (168 instead of ~225).  The compiler spills a few values, mostly
+// reloaded in the sampling step and the launch epilogue; the extra wave hides
+// more of the LDS round trips (16384 x 32 FP32: 18.1 -> 17.5 ms per 5000-step
+// launch; 16384 x 128 at 64 x 2: 31.9 -> 27.0 ms per 2000 steps; 16384 x 32
+// FP64: 13.9 -> 12.7 ms per 1000 steps).  Two-bead FP64 cannot reach 3
+// waves and is left to the compiler.
 template <typename T, int B>
-constexpr int kStepWavesPerEu = (std::is_same<T, float>::value && B == 1) ? 5 : 1;
+constexpr int kStepWavesPerEu = std::is_same<T, float>::value ? (B == 1 ? 5 : 4) : (B == 1 ? 3 : 1);
 
 template <typename T, int W, int B, bool K1>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>)))
