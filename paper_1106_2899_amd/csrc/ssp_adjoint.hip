@@ -102,7 +102,11 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     const double ddt = a.ph.dt;
     T kap[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
+    for (int q = 0; q < 9; ++q) {
+        kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
+        // one chain per wavefront: its element's kappa is wave-uniform
+        if constexpr (W == kWaveSize) kap[q] = wave_uniform(kap[q]);
+    }
     const v3<T>* trajR = reinterpret_cast<const v3<T>*>(a.traj);
     const v3<T>* trajA = reinterpret_cast<const v3<T>*>(a.traj2);
     T* lam = reinterpret_cast<T*>(a.lam);
@@ -136,6 +140,10 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 dinv[3 * r + c] = T(-(Mi[3 * r] * K[c] + Mi[3 * r + 1] * K[3 + c] + Mi[3 * r + 2] * K[6 + c]) / det);
+        if constexpr (W == kWaveSize) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dinv[q] = wave_uniform(dinv[q]);
+        }
     }
     const int ca = (a.comp < 3) ? a.comp : (a.comp == 3 ? 0 : (a.comp == 4 ? 1 : 2));
     const int cb = (a.comp < 3) ? a.comp : (a.comp == 3 ? 1 : (a.comp == 4 ? 2 : 0));

@@ -41,6 +41,18 @@ __device__ __forceinline__ uint4 draw(uint32_t purpose, uint32_t index, uint32_t
                   k0, k1);
 }
 
+// A value that every lane of the wavefront holds, moved to a scalar register
+// (frees VGPRs; only valid when the caller knows the value is wave-uniform).
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readfirstlane(p.x), __builtin_amdgcn_readfirstlane(p.y)));
+}
+
 // u = ((w >> 9) + 1/2) 2^-23: 23 random bits, exactly representable in
 // binary32 and binary64, never 0 or 1.
 template <typename T> __device__ __forceinline__ T u01(uint32_t w);

@@ -183,6 +183,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     for (int q = 0; q < 9; ++q) {
         const double kq = valid ? a.kappa[9 * elem + q] : 0.0;
         kdt[q] = T(a.ph.dt * kq);
+        // one chain per wavefront: its element's kappa is wave-uniform
+        if constexpr (W == kWaveSize) kdt[q] = wave_uniform(kdt[q]);
         has_flow |= kq != 0.0;
     }
     const bool flow = wave_any(has_flow);
