@@ -313,8 +313,9 @@ int fail(ssp_handle* h, int code, const std::string& msg)
         if (e_ != hipSuccess) return fail((h), SSP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// ck_end (optional): where the last launch also writes the final state.
 int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, int8_t* rec_s = nullptr,
-                  int64_t rec_g0 = 0)
+                  int64_t rec_g0 = 0, const State* ck_end = nullptr)
 {
     const ssp_config& k = h->res.cfg;
     const int64_t M = k.n_chains;
@@ -345,6 +346,7 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
             a.flags = h->flags();
             a.rec_s = rec_s;
             a.rec_g0 = rec_g0;
+            if (ck_end && done + m == n) a.ck_end = *ck_end;
             a.total = h->res.total_beads;
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
         }
@@ -825,10 +827,13 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
     int8_t* rows = reinterpret_cast<int8_t*>(rec + R.rows);
     const int64_t g0 = h->steps;
     HIPCHK(h, launch_rec_s0(h->st().s, rows, h->res.total_beads, s));
+    // checkpoint 0 is a copy of the state; each segment's last launch writes
+    // the next checkpoint from its epilogue
+    HIPCHK(h, launch_copy_bytes(rec + R.ckpts, h->state, h->lay.state_total, s));
     for (int c = 0; c < R.n_seg; ++c) {
-        HIPCHK(h, launch_copy_bytes(rec + R.ckpts + (size_t)c * h->lay.state_total, h->state, h->lay.state_total, s));
         const int64_t m = std::min<int64_t>(ckpt_every, window - (int64_t)c * ckpt_every);
-        int rc = enqueue_steps(h, m, kappa_dev, s, rows, g0);
+        const State next = state_at(h, rec + R.ckpts + (size_t)(c + 1) * h->lay.state_total);
+        int rc = enqueue_steps(h, m, kappa_dev, s, rows, g0, c + 1 < R.n_seg ? &next : nullptr);
         if (rc) return rc;
         const int64_t q = samples_between(h->steps, m, h->res.cfg.sample_every);
         h->steps += m;

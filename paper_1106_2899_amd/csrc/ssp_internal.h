@@ -72,6 +72,7 @@ struct StepArgs {
     uint32_t* flags;
     // adjoint support (all optional)
     int8_t* rec_s;         // [window+1][total]: slot state after step g stored at row g + 1 - rec_g0
+    State ck_end;          // optional (r0 null: off): a second copy of the final state, in the state-buffer layout
     int64_t rec_g0;
     const int8_t* replay_s;  // [window+1][total], rows as rec_s: replay these slot states instead of deciding them
     int64_t total;         // beads (= slots) in the ensemble
