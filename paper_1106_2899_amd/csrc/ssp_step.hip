@@ -639,28 +639,37 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         if (a.sample_every > 0) phase = (phase + 1 == a.sample_every) ? 0 : phase + 1;
     }
 
-    // the final state, and a second copy of it when asked (the next
-    // checkpoint of a recorded window)
-    auto store_state = [&](const State& dst) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = li * B + b;
+        if (i < n) {
+            finite_ok &= finite3(rh[b]);
+            st3<T>(a.st.r0, off + i, rh[b]);
+            st3<T>(a.st.a0, off + i, ah[b]);
+            if constexpr (kComp) {
+                st3<T>(a.st.r1, off + i, rl[b]);
+                st3<T>(a.st.a1, off + i, al[b]);
+            }
+            a.st.s[off + i] = s[b];
+        }
+    }
+    // a second copy of the final state when asked (the next checkpoint of a
+    // recorded window)
+    if (a.ck_end.r0) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
             if (i < n) {
-                st3<T>(dst.r0, off + i, rh[b]);
-                st3<T>(dst.a0, off + i, ah[b]);
+                st3<T>(a.ck_end.r0, off + i, rh[b]);
+                st3<T>(a.ck_end.a0, off + i, ah[b]);
                 if constexpr (kComp) {
-                    st3<T>(dst.r1, off + i, rl[b]);
-                    st3<T>(dst.a1, off + i, al[b]);
+                    st3<T>(a.ck_end.r1, off + i, rl[b]);
+                    st3<T>(a.ck_end.a1, off + i, al[b]);
                 }
-                dst.s[off + i] = s[b];
+                a.ck_end.s[off + i] = s[b];
             }
         }
-    };
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-        if (li * B + b < n) finite_ok &= finite3(rh[b]);
-    store_state(a.st);
-    if (a.ck_end.r0) store_state(a.ck_end);
+    }
     if constexpr (RP) {
 #pragma unroll
         for (int b = 0; b < B; ++b)
