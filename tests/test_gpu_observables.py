@@ -183,20 +183,27 @@ def test_nonfinite_state_is_reported():
     assert ei.value.code == -4
 
 
-def test_trajectory_does_not_depend_on_the_mapping():
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_trajectory_does_not_depend_on_the_mapping(precision):
+    """Every mapping that holds these chains, in both precisions (each kernel
+    variant with its own register budget and spills): the state is bitwise
+    the same; the element series (stress sampled every 5 steps) agrees to
+    1e-12, since a mapping may change the order of the FP64 lane sums."""
     N = [20, 24, 31, 17] * 16
     kap = [[0, 0.4, 0], [0, 0, 0], [0, 0, 0]]
-    ref = None
+    ref = ref_ser = None
     for W, B in [(32, 1), (64, 1), (16, 2), (32, 2), (64, 2)]:
-        e = _ens(N, precision="fp32", seed=21, corr_levels=0)
+        e = _ens(N, precision=precision, seed=21, corr_levels=0, sample_every=5, series_capacity=30)
         e.set_mapping(17, 31, W, B)
         e.init().step(150, kap)
         st = [x.cpu() for x in e.state()]
+        ser = e.element_series().cpu().numpy()
         if ref is None:
-            ref = st
+            ref, ref_ser = st, ser
         else:
             for x, y in zip(ref, st):
                 assert torch.equal(x, y), (W, B)
+            np.testing.assert_allclose(ser, ref_ser, rtol=1e-12, atol=1e-12 * np.abs(ref_ser).max())
         e.close()
 
 
