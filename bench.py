@@ -224,7 +224,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU: the step path runs on a single MI355X (--gpus 1); sharding across GPUs is described, not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -97,11 +97,10 @@ __device__ __forceinline__ v3<double> normals3_f64_scaled(uint4 w, double c)
     const double u0 = u01<double>(w.x), u1 = u01<double>(w.y), u2 = u01<double>(w.z), u3 = u01<double>(w.w);
     const double r1 = sqrt(c * log(u0));
     const double r2 = sqrt(c * log(u2));
-    const double t1 = 2.0 * M_PI * u1;
-    const double t2 = 2.0 * M_PI * u3;
+    // sin/cos of pi (2u): 2u is exact, so no range reduction by 2 pi
     double s1, c1;
-    sincos(t1, &s1, &c1);
-    return {r1 * c1, r1 * s1, r2 * cos(t2)};
+    sincospi(2.0 * u1, &s1, &c1);
+    return {r1 * c1, r1 * s1, r2 * cospi(2.0 * u3)};
 }
 __device__ __forceinline__ v3<float> normals3_f32(uint4 w) { return normals3_f32_scaled(w, -1.38629436111989061883f); }
 __device__ __forceinline__ v3<double> normals3_f64(uint4 w) { return normals3_f64_scaled(w, -2.0); }
@@ -119,7 +118,7 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double c, d
 {
     const double r = sqrt(c * log(u01<double>(wa)));
     double s, co;
-    sincos(2.0 * M_PI * u01<double>(wb), &s, &co);
+    sincospi(2.0 * u01<double>(wb), &s, &co);
     cs = r * co;
     sn = r * s;
 }
