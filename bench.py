@@ -119,7 +119,10 @@ def run_gpu(precision, md_steps, steps, warmup, timing=False, use_graph=True):
 
 def adjoint_ratio(chains=65536, beads=64, window=2000, ckpt=100, rate=0.01, reps=2):
     """Adjoint/forward time ratio on the differentiation workload: (recorded
-    forward + checkpointed reverse pass) / plain forward of the same window."""
+    forward + reverse pass) / plain forward of the same window.  Two ways: a
+    checkpoint every `ckpt` steps with each segment replayed in the reverse
+    pass, and the window as one segment whose forward stores the trajectory
+    (no replay; about 25 B of HBM per bead-step)."""
     import torch
 
     from paper_1106_2899_amd.ensemble import Ensemble
@@ -128,36 +131,47 @@ def adjoint_ratio(chains=65536, beads=64, window=2000, ckpt=100, rate=0.01, reps
     kap[0, 1] = rate
     e = Ensemble(beads, chains, precision="fp32", seed=5, sample_every=SAMPLE_EVERY, corr_levels=0, use_graph=True)
     e.init()
-    e.forward_record(window, ckpt, kap)
-    e.adjoint()
     e.step(window, kap)  # warm-up (graph capture)
     torch.cuda.synchronize()
-    t_fwd = t_rec = t_rev = 0.0
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        e.step(window, kap)
+
+    def timed(every):
+        e.forward_record(window, every, kap)  # warm-up (buffer allocation)
+        e.adjoint()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        e.forward_record(window, ckpt, kap)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        g = e.adjoint()
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        t_fwd += t1 - t0
-        t_rec += t2 - t1
-        t_rev += t3 - t2
-    assert torch.isfinite(g).all()
+        t_fwd = t_rec = t_rev = 0.0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            e.step(window, kap)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            e.forward_record(window, every, kap)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            g = e.adjoint()
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            t_fwd += t1 - t0
+            t_rec += t2 - t1
+            t_rev += t3 - t2
+        assert torch.isfinite(g).all()
+        return {
+            "checkpoint_every": every,
+            "recording_GB": e._rec_bytes / 1e9,
+            "forward_ms": t_fwd / reps * 1e3,
+            "recorded_forward_ms": t_rec / reps * 1e3,
+            "reverse_ms": t_rev / reps * 1e3,
+            "adjoint_over_forward": (t_rec + t_rev) / t_fwd,
+        }
+
+    out = {"workload": f"adjoint_{chains}x{beads}", "window": window}
+    out.update(timed(ckpt))
+    try:
+        out["stored_window"] = timed(window)
+    except torch.OutOfMemoryError as err:
+        out["stored_window"] = {"skipped": f"recording buffer does not fit: {err}"[:200]}
     e.close()
-    return {
-        "workload": f"adjoint_{chains}x{beads}",
-        "window": window,
-        "checkpoint_every": ckpt,
-        "forward_ms": t_fwd / reps * 1e3,
-        "recorded_forward_ms": t_rec / reps * 1e3,
-        "reverse_ms": t_rev / reps * 1e3,
-        "adjoint_over_forward": (t_rec + t_rev) / t_fwd,
-    }
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_configs(md_steps=1000, launches=3):
@@ -249,7 +263,7 @@ def main():
     achieved = slots * (bead_steps / launches) / per_launch_s
     roofline = {
         "bound": "alu",
-        "kernel": "k_step<float,32,1,false>",
+        "kernel": "k_step<float,32,1,false,false>",
         "achieved": achieved,
         "peak": PEAK_LANE_SLOTS,
         "unit": "VALU lane-slots/s",

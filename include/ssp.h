@@ -224,19 +224,27 @@ int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead,
  * the replay of one segment. */
 
 /* Bytes of the caller-owned recording buffer for a window of `window` steps
- * with a checkpoint every `ckpt_every` steps. */
+ * with a checkpoint every `ckpt_every` steps.  The buffer holds the slot rows
+ * ((window + 1) x total beads, 1 byte each), the checkpoints, and the
+ * positions and anchors of one segment (2 (min(ckpt_every, window) + 1) x
+ * total beads x 3 values of the path's precision): with ckpt_every >= window
+ * that is the whole window (about 25 B per bead-step in FP32). */
 int ssp_adjoint_bytes(const ssp_handle* h, int64_t window, int32_t ckpt_every, size_t* bytes);
 
 /* Advances the ensemble by `window` steps exactly like ssp_step (same
  * trajectory, samples and counters) while recording the slot state after every
  * step and a state checkpoint every ckpt_every steps into rec_dev (256-byte
- * aligned, ssp_adjoint_bytes long).  kappa_dev as in ssp_step.  Asynchronous. */
+ * aligned, ssp_adjoint_bytes long).  With ckpt_every >= window the window is
+ * one segment and the forward also stores its positions and the anchors the
+ * reverse pass needs, so that ssp_adjoint replays nothing (memory for time).
+ * kappa_dev as in ssp_step.  Asynchronous. */
 int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const double* kappa_dev, void* rec_dev,
                        ssp_stream stream);
 
 /* Reverse pass over the last recorded window: for every checkpoint segment,
  * last to first, replays the segment from its checkpoint (bitwise the same
- * trajectory) and runs the adjoint recursion through it.  grad_dev [M][10]
+ * trajectory; a one-segment window uses the trajectory its forward stored)
+ * and runs the adjoint recursion through it.  grad_dev [M][10]
  * FP64 receives dJ_k/dkappa_ab (row-major, 9 values) and dJ_k/dN_s for
  * J_k = sigma_component of chain k at the end of the window (component 0..5
  * = xx yy zz xy yz zx).  kappa_dev must hold the velocity gradient of the

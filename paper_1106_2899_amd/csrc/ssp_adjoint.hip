@@ -69,7 +69,10 @@ template <typename T> __device__ __forceinline__ v3<T> dsigma(v3<T> b, int ca, i
     return g;
 }
 
-template <typename T, int W, int B>
+// MV: also check that each pair of consecutive slot rows is a move the step
+// can make.  Without it only a segment's first step is checked: a replay
+// checks the rest of the segment it re-creates, from its checkpoint.
+template <typename T, int W, int B, bool MV>
 __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
 {
     constexpr int kChainsPerWave = kWaveSize / W;
@@ -197,6 +200,9 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     // Recorded slot rows are checked before use as LDS indices (where they are
     // used, not where they are loaded, so that a prefetch is not waited for):
     // a value outside -1..n-1 reads as an empty slot and latches kFlagReplay.
+    // So does a pair of rows no step can produce (a spring that moves by more
+    // than one bead, or is created away from an end): checked at every step
+    // with MV, otherwise at the segment's first.
     bool bad_row = false;
     auto checked = [&](int v) -> int {
         const bool ok = v >= -1 && v < n;
@@ -242,6 +248,9 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             sm[b] = checked(s_pre[b]);
             s1[b] = s_next[b];
             s_next[b] = sm[b];
+            if (MV || m == 0)
+                bad_row |= sm[b] >= 0 ? (s1[b] >= 0 && (s1[b] < sm[b] - 1 || s1[b] > sm[b] + 1))
+                                      : (s1[b] > 0 && s1[b] < n - 1);
             Rm[b] = R_pre[b];
             cr[b] = sm[b] < 0 && s1[b] >= 0;
             any_cr |= cr[b];
@@ -409,7 +418,10 @@ template <typename T, int W, int B> hipError_t launch_t(const AdjointArgs& a, hi
     constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
     const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
     if (groups == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_adjoint<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    if (a.check_moves)
+        hipLaunchKernelGGL((k_adjoint<T, W, B, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<T, W, B, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     return hipGetLastError();
 }
 

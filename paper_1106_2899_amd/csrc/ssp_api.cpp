@@ -248,6 +248,7 @@ struct ssp_handle {
         const void* ptr = nullptr;
         int64_t window = 0, g0 = 0;
         int32_t ckpt = 0;
+        bool stored = false;  // the forward stored the trajectory (one segment)
     } rec;
     bool initialized = false;
     int64_t steps = 0, corr_samples = 0, series_samples = 0;
@@ -315,7 +316,7 @@ int fail(ssp_handle* h, int code, const std::string& msg)
 
 // ck_end (optional): where the last launch also writes the final state.
 int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, int8_t* rec_s = nullptr,
-                  int64_t rec_g0 = 0, const State* ck_end = nullptr)
+                  int64_t rec_g0 = 0, const State* ck_end = nullptr, void* traj = nullptr, void* traj2 = nullptr)
 {
     const ssp_config& k = h->res.cfg;
     const int64_t M = k.n_chains;
@@ -347,6 +348,8 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
             a.rec_s = rec_s;
             a.rec_g0 = rec_g0;
             if (ck_end && done + m == n) a.ck_end = *ck_end;
+            a.traj = traj;
+            a.traj2 = traj2;
             a.total = h->res.total_beads;
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
         }
@@ -773,6 +776,7 @@ RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
     const size_t beads = (size_t)h->res.total_beads;
     const size_t t = h->res.cfg.precision == SSP_FP32 ? 4 : 8;
     L.n_seg = (int)((window + ckpt - 1) / ckpt);
+    const size_t seg = (size_t)std::min<int64_t>(ckpt, window);  // steps of the longest segment
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -783,8 +787,8 @@ RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
     L.ckpts = take((size_t)L.n_seg * h->lay.state_total);
     L.scratch = take(h->lay.state_total);
     L.ctrl = take(sizeof(int64_t) * kCtrlWords);
-    L.traj = take((size_t)(ckpt + 1) * beads * 3 * t);
-    L.traj2 = take((size_t)(ckpt + 1) * beads * 3 * t);
+    L.traj = take((seg + 1) * beads * 3 * t);
+    L.traj2 = take((seg + 1) * beads * 3 * t);
     L.lam = take(beads * 6 * t);
     L.total = o;
     return L;
@@ -827,13 +831,18 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
     int8_t* rows = reinterpret_cast<int8_t*>(rec + R.rows);
     const int64_t g0 = h->steps;
     HIPCHK(h, launch_rec_s0(h->st().s, rows, h->res.total_beads, s));
-    // checkpoint 0 is a copy of the state; each segment's last launch writes
-    // the next checkpoint from its epilogue
-    HIPCHK(h, launch_copy_bytes(rec + R.ckpts, h->state, h->lay.state_total, s));
+    // A one-segment window stores its trajectory as it runs, and the reverse
+    // pass starts from that.  Otherwise checkpoint 0 is a copy of the state,
+    // each segment's last launch writes the next checkpoint from its
+    // epilogue, and the reverse pass replays each segment from its checkpoint.
+    const bool store = R.n_seg == 1;
+    if (!store) HIPCHK(h, launch_copy_bytes(rec + R.ckpts, h->state, h->lay.state_total, s));
+    h->rec.ptr = nullptr;  // not a usable recording until the window is complete
     for (int c = 0; c < R.n_seg; ++c) {
         const int64_t m = std::min<int64_t>(ckpt_every, window - (int64_t)c * ckpt_every);
         const State next = state_at(h, rec + R.ckpts + (size_t)(c + 1) * h->lay.state_total);
-        int rc = enqueue_steps(h, m, kappa_dev, s, rows, g0, c + 1 < R.n_seg ? &next : nullptr);
+        int rc = enqueue_steps(h, m, kappa_dev, s, rows, g0, c + 1 < R.n_seg ? &next : nullptr,
+                               store ? rec + R.traj : nullptr, store ? rec + R.traj2 : nullptr);
         if (rc) return rc;
         const int64_t q = samples_between(h->steps, m, h->res.cfg.sample_every);
         h->steps += m;
@@ -844,6 +853,7 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
     h->rec.window = window;
     h->rec.ckpt = ckpt_every;
     h->rec.g0 = g0;
+    h->rec.stored = store;
     return SSP_OK;
 }
 
@@ -866,31 +876,35 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
     for (int c = R.n_seg - 1; c >= 0; --c) {
         const int64_t m = std::min<int64_t>(h->rec.ckpt, h->rec.window - (int64_t)c * h->rec.ckpt);
         // replay the segment from its checkpoint, storing the trajectory
-        HIPCHK(h, launch_copy_bytes(scratch, rec + R.ckpts + (size_t)c * h->lay.state_total, h->lay.state_total, s));
-        HIPCHK(h, launch_set_ctrl_steps(sctrl, h->rec.g0 + (int64_t)c * h->rec.ckpt, s));
-        for (auto& g : h->groups) {
-            StepArgs a{};
-            a.st = state_at(h, scratch);
-            a.ct = h->ct();
-            a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
-            a.n_tasks = g.second.second;
-            a.kappa = kappa_dev;
-            a.thr = reinterpret_cast<const uint32_t*>(h->work + h->lay.thr);
-            a.thr_destroy = threshold(std::min(k.dt / k.zeta_s * 1.0, 1.0));
-            a.construct_rule = k.construct_rule;
-            a.ph = h->phys();
-            a.ctrl = sctrl;
-            a.n_steps = (int32_t)m;
-            a.sample_every = 0;
-            a.samples = nullptr;
-            a.n_chains = k.n_chains;
-            a.flags = h->flags();
-            a.total = h->res.total_beads;
-            a.traj = rec + R.traj;
-            a.traj2 = rec + R.traj2;
-            a.replay_s = rows;  // the recorded slot states, replayed
-            a.rec_g0 = h->rec.g0;
-            HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
+        // (a one-segment window has it from the forward)
+        if (!h->rec.stored) {
+            HIPCHK(h, launch_copy_bytes(scratch, rec + R.ckpts + (size_t)c * h->lay.state_total,
+                                        h->lay.state_total, s));
+            HIPCHK(h, launch_set_ctrl_steps(sctrl, h->rec.g0 + (int64_t)c * h->rec.ckpt, s));
+            for (auto& g : h->groups) {
+                StepArgs a{};
+                a.st = state_at(h, scratch);
+                a.ct = h->ct();
+                a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
+                a.n_tasks = g.second.second;
+                a.kappa = kappa_dev;
+                a.thr = reinterpret_cast<const uint32_t*>(h->work + h->lay.thr);
+                a.thr_destroy = threshold(std::min(k.dt / k.zeta_s * 1.0, 1.0));
+                a.construct_rule = k.construct_rule;
+                a.ph = h->phys();
+                a.ctrl = sctrl;
+                a.n_steps = (int32_t)m;
+                a.sample_every = 0;
+                a.samples = nullptr;
+                a.n_chains = k.n_chains;
+                a.flags = h->flags();
+                a.total = h->res.total_beads;
+                a.traj = rec + R.traj;
+                a.traj2 = rec + R.traj2;
+                a.replay_s = rows;  // the recorded slot states, replayed
+                a.rec_g0 = h->rec.g0;
+                HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
+            }
         }
         for (auto& g : h->groups) {
             AdjointArgs a{};
@@ -912,6 +926,7 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.seed_lambda = (c == R.n_seg - 1) ? 1 : 0;
             a.init_terms = (c == 0 && init_window && h->rec.g0 == 0) ? 1 : 0;
             a.flags = h->flags();
+            a.check_moves = h->rec.stored ? 1 : 0;  // a replay checks the rows it re-creates
             HIPCHK(h, launch_adjoint(k.precision, g.first.W, g.first.B, a, s));
         }
     }

@@ -92,15 +92,16 @@ struct AdjointArgs {
     int64_t rec_g0;         // global step index of the window start
     int64_t m0;             // window index of the segment start
     int32_t len;            // steps in the segment
-    const void* traj;       // [len+1][total] T3: R (replay output)
-    const void* traj2;      // [len+1][total] T3: A at row len and of the springs destroyed in each step (replay output)
+    const void* traj;       // [len+1][total] T3: R (replay or storing-forward output)
+    const void* traj2;      // [len+1][total] T3: A at row len and of the springs destroyed in each step
     void* lam;              // [total][6] T: dJ/dR, dJ/dA carried between segments
     double* grad;           // [M][10]: dJ/dkappa (row-major), dJ/dN_s (accumulated)
-    uint32_t* flags;        // kFlagReplay: a recorded slot row out of range (read as empty)
+    uint32_t* flags;        // kFlagReplay: a recorded slot row out of range (read as empty) or an impossible move
     int64_t total;
     int32_t comp;           // objective component 0..5 (xx yy zz xy yz zx)
     int32_t seed_lambda;    // 1 for the last segment: start from dJ/dR at its end
     int32_t init_terms;     // 1: include the N_s dependence of the sampled initial anchors (segment at window start)
+    int32_t check_moves;    // 1: check every pair of rows is a possible step (no replay has checked them)
 };
 
 struct CorrArgs {

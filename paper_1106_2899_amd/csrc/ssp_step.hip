@@ -136,7 +136,10 @@ template <typename T, int B> struct WaveLds {
 // RP: replay of a recorded run: the slot state after each step is read from
 // the recorded rows instead of being decided (no hop or construction draws or
 // probabilities); positions and anchors follow bit for bit.
-template <typename T, int W, int B, bool K1, bool RP>
+// ST: a recorded forward that also stores the trajectory the replay would
+// (positions every step, the anchors the adjoint cannot rebuild), so that the
+// reverse pass of a one-segment window needs no replay.
+template <typename T, int W, int B, bool K1, bool RP, bool ST>
 __device__ __forceinline__ void step_body(const StepArgs& a)
 {
     constexpr bool kComp = std::is_same<T, float>::value;  // (hi, lo) position sums
@@ -259,12 +262,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     bonds_and_records();
     refresh_offsets();
 
-    // Replay output: R after every step (row 0: launch start), FP32 positions
-    // rounded from hi + lo.  Anchors are written only where the adjoint cannot
-    // recover them by running the advection backwards: for every slot at the
-    // launch end, and for each spring destroyed in a step, at that step's row.
+    const int64_t g0 = a.ctrl[kCtrlSteps];
+
+    // Trajectory output: R after every step (row 0: the state before the
+    // first step), FP32 positions rounded from hi + lo.  Anchors are written
+    // only where the adjoint cannot recover them by running the advection
+    // backwards: for every slot at the launch end, and for each spring
+    // destroyed in a step, at that step's row.  A replay counts rows from its
+    // launch (one segment); a storing forward from the recorded window's
+    // start, however the window is split into launches.
+    constexpr bool kTraj = RP || ST;
+    const int64_t trow0 = RP ? 0 : g0 - a.rec_g0;
     auto store_r = [&](int row) {
-        const int64_t e = (int64_t)row * a.total + off;
+        const int64_t e = (trow0 + row) * a.total + off;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
@@ -272,11 +282,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         }
     };
     auto store_a = [&](int row, int b) {
-        reinterpret_cast<v3<T>*>(a.traj2)[(int64_t)row * a.total + off + li * B + b] = ah[b] + al[b];
+        reinterpret_cast<v3<T>*>(a.traj2)[(trow0 + row) * a.total + off + li * B + b] = ah[b] + al[b];
     };
-    if constexpr (RP) store_r(0);
+    if constexpr (kTraj) store_r(0);
 
-    const int64_t g0 = a.ctrl[kCtrlSteps];
     bool finite_ok = true;
 
     // Random streams come in step pairs (2k, 2k+1), three Philox blocks per
@@ -537,7 +546,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
                 }
             } else if (j < n) {
                 if (s[b] >= 0) {
-                    if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) s[b] = -1;
+                    if ((s[b] == 0 || s[b] == n - 1) && uw < a.thr_destroy) {
+                        s[b] = -1;
+                        destroyed[b] = true;
+                    }
                 } else if (!K1 || j == first_empty) {
                     if (uw < t1)
                         create_at[b] = 0;
@@ -575,7 +587,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
             for (int b = 0; b < B; ++b)
                 if (li * B + b < n) row[li * B + b] = (int8_t)s[b];
         }
-        if constexpr (RP) {
+        if constexpr (kTraj) {
             store_r(step + 1);
 #pragma unroll
             for (int b = 0; b < B; ++b)
@@ -670,7 +682,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
             }
         }
     }
-    if constexpr (RP) {
+    if constexpr (kTraj) {
 #pragma unroll
         for (int b = 0; b < B; ++b)
             if (li * B + b < n) store_a(a.n_steps, b);
@@ -690,11 +702,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
 template <typename T, int B>
 constexpr int kStepWavesPerEu = std::is_same<T, float>::value ? (B == 1 ? 5 : 4) : (B == 1 ? 3 : 1);
 
-template <typename T, int W, int B, bool K1>
+template <typename T, int W, int B, bool K1, bool ST>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>)))
 k_step(StepArgs a)
 {
-    step_body<T, W, B, K1, false>(a);
+    step_body<T, W, B, K1, false, ST>(a);
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
@@ -703,7 +715,7 @@ k_step(StepArgs a)
 template <typename T, int W, int B>
 __global__ void __launch_bounds__(kGroupThreads) k_replay(StepArgs a)
 {
-    step_body<T, W, B, false, true>(a);
+    step_body<T, W, B, false, true, false>(a);
 }
 
 template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipStream_t s)
@@ -713,10 +725,14 @@ template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipSt
     if (groups == 0) return hipSuccess;
     if (a.replay_s)
         hipLaunchKernelGGL((k_replay<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    else if (a.traj && a.construct_rule == 1)
+        hipLaunchKernelGGL((k_step<T, W, B, true, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+    else if (a.traj)
+        hipLaunchKernelGGL((k_step<T, W, B, false, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     else if (a.construct_rule == 1)
-        hipLaunchKernelGGL((k_step<T, W, B, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+        hipLaunchKernelGGL((k_step<T, W, B, true, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_step<T, W, B, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
+        hipLaunchKernelGGL((k_step<T, W, B, false, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     return hipGetLastError();
 }
 

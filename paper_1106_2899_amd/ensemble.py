@@ -132,6 +132,7 @@ class Ensemble:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ssp_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._rec_t, self._rec_bytes = None, 0  # the recording buffer can be most of the device
 
     def __del__(self):
         try:

@@ -3,6 +3,7 @@
     python -m paper_1106_2899_amd.profile_run step   # step kernel, 16384 x N=32, 3 launches of 5000 steps
     python -m paper_1106_2899_amd.profile_run copy   # 1 GiB read + 1 GiB write elementwise copy (counter calibration)
     python -m paper_1106_2899_amd.profile_run adjoint  # 65536 x N=64 under shear 0.01: forward, recorded forward, reverse
+    python -m paper_1106_2899_amd.profile_run adjoint_stored  # the same window as one stored segment (no replay)
 """
 from __future__ import annotations
 
@@ -38,6 +39,10 @@ def adjoint(chains: int = 65536, beads: int = 64, window: int = 2000, ckpt: int 
     print("adjoint window:", window, "checkpoint every:", ckpt, "bead-steps per pass:", chains * beads * window, flush=True)
 
 
+def adjoint_stored() -> None:
+    adjoint(ckpt=2000)
+
+
 def copy(nbytes: int = 1 << 30) -> None:
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -48,4 +53,4 @@ def copy(nbytes: int = 1 << 30) -> None:
 
 
 if __name__ == "__main__":
-    {"step": step, "copy": copy, "adjoint": adjoint}[sys.argv[1]]()
+    {"step": step, "copy": copy, "adjoint": adjoint, "adjoint_stored": adjoint_stored}[sys.argv[1]]()

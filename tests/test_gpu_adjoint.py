@@ -1,5 +1,7 @@
 """GPU pathwise adjoint (recorded window, checkpointed replay, reverse pass)
-against the oracle's discrete adjoint on the same seeded inputs.
+against the oracle's discrete adjoint on the same seeded inputs.  A window
+recorded as one segment (checkpoint interval >= window) stores its trajectory
+in the forward and is differentiated without a replay; the tests run both.
 
 Tolerance: FP64 path 1e-9 relative to the largest gradient entry; FP32 path
 1e-4 (the adjoint recursion runs in the path's precision, gradients are
@@ -42,11 +44,13 @@ def _check(got, want, rtol):
     assert err.max() <= rtol, (err.max(axis=0), rtol)
 
 
+@pytest.mark.parametrize("ckpt", [64, 300], ids=["checkpointed", "stored"])
 @pytest.mark.parametrize("precision,rtol", [("fp64", 1e-9), ("fp32", 1e-4)])
-def test_adjoint_matches_oracle_shear(precision, rtol):
-    N, M, T, ckpt = 12, 24, 300, 64  # segments 64, 64, 64, 64, 44
+def test_adjoint_matches_oracle_shear(precision, rtol, ckpt):
+    N, M, T = 12, 24, 300  # segments 64, 64, 64, 64, 44, or one stored window
     kap = _shear(0.3)
-    e = _ens(N, M, precision=precision, seed=5, corr_levels=0).init()
+    # launches of 70 steps: a stored window spans several launches
+    e = _ens(N, M, precision=precision, seed=5, corr_levels=0, max_steps_per_launch=70).init()
     e.forward_record(T, ckpt, kap)
     got = e.adjoint(component=3).cpu().numpy()
     want, o = _oracle_grad([N] * M, 5, T, kap, 3)
@@ -65,11 +69,13 @@ def test_adjoint_matches_oracle_mixed_lengths_elongation_fp64():
     _check(got, want, 1e-9)
 
 
-def test_forward_record_advances_exactly_like_step():
+@pytest.mark.parametrize("ckpt", [40, 230], ids=["checkpointed", "stored"])
+def test_forward_record_advances_exactly_like_step(ckpt):
     kap = _shear(0.2)
-    a = _ens(20, 32, precision="fp32", seed=3, corr_levels=4, corr_batches=4, sample_every=5).init()
-    b = _ens(20, 32, precision="fp32", seed=3, corr_levels=4, corr_batches=4, sample_every=5).init()
-    a.forward_record(230, 40, kap)
+    kw = dict(precision="fp32", seed=3, corr_levels=4, corr_batches=4, sample_every=5, max_steps_per_launch=100)
+    a = _ens(20, 32, **kw).init()
+    b = _ens(20, 32, **kw).init()
+    a.forward_record(230, ckpt, kap)
     b.step(230, kap)
     for x, y in zip(a.state(), b.state()):
         assert torch.equal(x, y)
@@ -100,15 +106,20 @@ def test_autograd_function_matches_adjoint_means():
     np.testing.assert_allclose(J.detach().cpu().numpy(), o.stress()[:, 3].reshape(E, per).mean(axis=1), rtol=1e-10)
 
 
-def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble():
-    """A slot row changed after ssp_forward_record (an impossible state, 100 in
-    a chain of N = 8) is caught where the replay and the adjoint read it (both
-    kernels check a row before using it, and read a bad entry as an empty
-    slot): ssp_adjoint fails, the ensemble's own state is untouched, and a new
-    recording differentiates normally."""
+@pytest.mark.parametrize("change", ["out_of_range", "impossible_move", "first_row"])
+@pytest.mark.parametrize("ckpt", [10, 40], ids=["checkpointed", "stored"])
+def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble(ckpt, change):
+    """A slot row changed after ssp_forward_record is caught where the replay
+    and the adjoint read it (both kernels check a row before using it, and read
+    a bad entry as an empty slot): either a state that cannot exist (100 in a
+    chain of N = 8), or one no step reaches from the row before (a spring that
+    appears in the middle of the chain), or a first row from which no step
+    reaches the second (which a replay, starting from its checkpoint, never
+    compares).  ssp_adjoint fails, the ensemble's own state is untouched, and a
+    new recording differentiates normally."""
     from paper_1106_2899_amd._lib import SspError
 
-    N, M, T, ckpt = 8, 64, 40, 10
+    N, M, T = 8, 64, 40
     kap = _shear(0.1)
     e = _ens(N, M, precision="fp32", seed=31, corr_levels=0).init()
     e.forward_record(T, ckpt, kap)
@@ -116,7 +127,18 @@ def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble():
     # slot rows: the first region of the recording buffer, [T + 1][N * M] int8
     off = e._rec_p - e._rec_t.data_ptr()
     rows = e._rec_t[off:off + (T + 1) * N * M].view(T + 1, N * M)
-    rows[20, 3] = 100
+    if change == "out_of_range":
+        rows[20, 3] = 100
+    elif change == "impossible_move":
+        r = rows.cpu().numpy().astype(np.int8)
+        empty = np.flatnonzero((r[19] == -1) & (r[20] == -1) & (r[21] == -1))
+        assert empty.size > 0
+        rows[20, int(empty[0])] = N // 2
+    else:
+        r = rows.cpu().numpy().astype(np.int8)
+        j = int(np.flatnonzero((r[0] >= 0) & (r[1] >= 0))[0])  # a spring held over step 0
+        s1 = int(r[1, j])
+        rows[0, j] = s1 + 3 if s1 + 3 < N else s1 - 3
     torch.cuda.synchronize()
     with pytest.raises(SspError, match="recorded slot rows"):
         e.adjoint(component=3)
@@ -126,12 +148,30 @@ def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble():
     assert torch.isfinite(g).all()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_stored_window_gives_the_checkpointed_gradients(precision):
+    """The same window differentiated from its stored trajectory and by
+    checkpointed replay: FP64 gradients agree to rounding (only the order of
+    the FP64 sums differs); FP32 ones to the path's tolerance, since a
+    checkpointed reverse pass restarts the backward anchor advection from each
+    segment's FP32 anchors."""
+    N, M, T = 16, 48, 250
+    kap = _shear(0.25)
+    got = {}
+    for ckpt in (50, T):
+        e = _ens(N, M, precision=precision, seed=21, corr_levels=0, max_steps_per_launch=60).init()
+        e.forward_record(T, ckpt, kap)
+        got[ckpt] = e.adjoint(component=3).cpu().numpy()
+    _check(got[T], got[50], 1e-12 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("ckpt", [48, 200], ids=["checkpointed", "stored"])
 @pytest.mark.parametrize("precision,rtol", [("fp64", 1e-9), ("fp32", 1e-4)])
-def test_adjoint_under_the_k1_construction_rule(precision, rtol):
+def test_adjoint_under_the_k1_construction_rule(precision, rtol, ckpt):
     """The reverse pass replays recorded slot states, whatever rule decided
     them: a window recorded under the K = 1 rule differentiates like the
-    oracle's run under the same rule."""
-    N, M, T, ckpt = 10, 24, 200, 48  # segments 48, 48, 48, 48, 8
+    oracle's run under the same rule, replayed or stored."""
+    N, M, T = 10, 24, 200  # segments 48, 48, 48, 48, 8, or one stored window
     kap = _shear(0.2)
     e = _ens(N, M, precision=precision, seed=8, corr_levels=0, construct_rule=1).init()
     e.forward_record(T, ckpt, kap)

@@ -102,21 +102,29 @@ def test_polydisperse_full_size_sampled_chains():
     _compare_chains(e, ids, w.n_beads, kchain, steps, w.seed)
 
 
-def test_differentiation_full_size_sampled_chains():
+@pytest.mark.parametrize("stored", [False, True], ids=["checkpointed", "stored_400"])
+def test_differentiation_full_size_sampled_chains(stored):
+    """All chains of the differentiation workload; the checkpointed window at
+    its full length, and a 400-step window recorded as one stored segment
+    (about 42 GB of recording; the full 2000-step one, 210 GB, is timed by the
+    benchmark)."""
     _need_gpu()
     from paper_1106_2899_amd.ensemble import Ensemble
     w = workloads.differentiation()
+    steps, ckpt = (400, 400) if stored else (w.steps, w.extra["checkpoint_every"])
     e = Ensemble(w.n_beads, precision="fp32", seed=w.seed, sample_every=10, corr_levels=0).init()
     kap = w.kappa.reshape(1, 9)
-    e.forward_record(w.steps, w.extra["checkpoint_every"], kap)
+    e.forward_record(steps, ckpt, kap)
     g = e.adjoint(component=3).cpu().numpy()
     ids = np.array([0, 7777, 40000, w.n_chains - 1], dtype=np.int64)
     o = oracle.Ensemble([int(w.n_beads[i]) for i in ids], chain_ids=ids, seed=w.seed).init()
-    Rt, At, St = o.run_record(w.steps, kap)
+    Rt, At, St = o.run_record(steps, kap)
     gk, gns = o.adjoint(Rt, At, St, kap, comp=3)
     R, A, S = (x.cpu().numpy() for x in e.state())
+    offsets = e.offsets
+    e.close()
     for q, k in enumerate(ids):
-        sl = slice(int(e.offsets[k]), int(e.offsets[k]) + 64)
+        sl = slice(int(offsets[k]), int(offsets[k]) + 64)
         if not np.array_equal(S[sl], o.S[o.off[q]:o.off[q] + 64]):
             continue  # a tie changed an event of this chain
         np.testing.assert_allclose(g[k, 1], gk[q, 0, 1], rtol=1e-3, atol=1e-4 * np.abs(gk[:, 0, 1]).max())
