@@ -122,7 +122,7 @@ def adjoint_ratio(chains=65536, beads=64, window=2000, ckpt=100, rate=0.01, reps
     forward + reverse pass) / plain forward of the same window.  Two ways: a
     checkpoint every `ckpt` steps with each segment replayed in the reverse
     pass, and the window as one segment whose forward stores the trajectory
-    (no replay; about 25 B of HBM per bead-step)."""
+    (no replay; about 13 B of HBM per bead-step)."""
     import torch
 
     from paper_1106_2899_amd.ensemble import Ensemble

@@ -226,9 +226,12 @@ int ssp_rng_normals(ssp_handle* h, int64_t chain_id, int64_t step, int32_t bead,
 /* Bytes of the caller-owned recording buffer for a window of `window` steps
  * with a checkpoint every `ckpt_every` steps.  The buffer holds the slot rows
  * ((window + 1) x total beads, 1 byte each), the checkpoints, and the
- * positions and anchors of one segment (2 (min(ckpt_every, window) + 1) x
- * total beads x 3 values of the path's precision): with ckpt_every >= window
- * that is the whole window (about 25 B per bead-step in FP32). */
+ * positions and anchors of one segment (2 (ckpt_every + 1) x total beads x 3
+ * values of the path's precision).  With ckpt_every >= window (a stored
+ * window) it holds instead the positions of the whole window ((window + 1) x
+ * total beads x 3 values), the anchors at its end, and a per-chain log of
+ * the anchors of destroyed springs sized from the creation rate: about 13 B
+ * per bead-step in FP32. */
 int ssp_adjoint_bytes(const ssp_handle* h, int64_t window, int32_t ckpt_every, size_t* bytes);
 
 /* Advances the ensemble by `window` steps exactly like ssp_step (same
@@ -253,7 +256,9 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
  * recorded slot row is checked as it is read (a state the step could have
  * produced from the one before); a recording changed since
  * ssp_forward_record fails with SSP_EINVAL, leaves the ensemble's own state
- * untouched and gives no valid gradients. */
+ * untouched and gives no valid gradients.  A stored window in which a chain
+ * destroyed more springs than its log holds (far beyond the expected count)
+ * fails with SSP_ESIZE; record such a window with checkpoints. */
 int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
                 double* grad_dev, ssp_stream stream);
 

@@ -11,8 +11,9 @@ window; the backward pass runs the library's reverse pass and returns
 dJ_e/drate_e and dJ_e/dN_s, conditioned on the recorded events and random
 normals.  With ckpt_every < window the reverse pass replays each checkpoint
 segment; with ckpt_every >= window the forward stores the whole trajectory
-(about 25 B per bead-step in FP32) and the reverse pass replays nothing.  N_s is a property of the ensemble: the value
-passed in must equal it (the gradient with respect to it is still returned).
+(about 13 B per bead-step in FP32) and the reverse pass replays nothing.
+N_s is a property of the ensemble: the value passed in must equal it (the
+gradient with respect to it is still returned).
 """
 from __future__ import annotations
 

@@ -69,10 +69,13 @@ template <typename T> __device__ __forceinline__ v3<T> dsigma(v3<T> b, int ca, i
     return g;
 }
 
-// MV: also check that each pair of consecutive slot rows is a move the step
-// can make.  Without it only a segment's first step is checked: a replay
+// SW: a stored window (one segment written by the storing forward): the
+// end-of-window anchors come from a single plane and destroyed springs'
+// anchors from the per-chain log, read back from its end; every pair of
+// consecutive slot rows is checked to be a move the step can make.  Without
+// SW (a replayed segment) only the segment's first step is checked: the replay
 // checks the rest of the segment it re-creates, from its checkpoint.
-template <typename T, int W, int B, bool MV>
+template <typename T, int W, int B, bool SW>
 __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
 {
     constexpr int kChainsPerWave = kWaveSize / W;
@@ -201,8 +204,10 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     // used, not where they are loaded, so that a prefetch is not waited for):
     // a value outside -1..n-1 reads as an empty slot and latches kFlagReplay.
     // So does a pair of rows no step can produce (a spring that moves by more
-    // than one bead, or is created away from an end): checked at every step
-    // with MV, otherwise at the segment's first.
+    // than one bead, is created away from an end, or is destroyed more than
+    // one bead away from an end, where no hop can take it): checked at every step
+    // with SW, otherwise at the segment's first.  With SW, so does a log that
+    // holds other than exactly one entry per destruction the rows show.
     bool bad_row = false;
     auto checked = [&](int v) -> int {
         const bool ok = v >= -1 && v < n;
@@ -231,10 +236,17 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         s_next[b] = (i < n) ? row_at(a.m0 + a.len, i) : -1;
         Ac[b] = {0.0, 0.0, 0.0};
         if (i < n) {
-            const v3<T> v = trajA[(int64_t)a.len * a.total + off + i];
+            const v3<T> v = SW ? trajA[off + i] : trajA[(int64_t)a.len * a.total + off + i];
             Ac[b] = {(double)v.x, (double)v.y, (double)v.z};
         }
     }
+    int64_t dcount = 0;  // SW: destruction-log entries not yet consumed
+    if constexpr (SW) {
+        dcount = valid ? a.dcnt[chain] : 0;
+        if (dcount > a.dcap) atomicOr(a.flags, kFlagLogOverflow);
+    }
+    const v3<T>* dlog = SW ? reinterpret_cast<const v3<T>*>(a.dlog) + (int64_t)chain * a.dcap : nullptr;
+    const uint64_t segm = W == kWaveSize ? ~0ull : (((1ull << W) - 1ull) << sb);
     if (a.len > 0) prefetch(a.len - 1);
 
     for (int m = a.len - 1; m >= 0; --m) {
@@ -248,17 +260,52 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             sm[b] = checked(s_pre[b]);
             s1[b] = s_next[b];
             s_next[b] = sm[b];
-            if (MV || m == 0)
-                bad_row |= sm[b] >= 0 ? (s1[b] >= 0 && (s1[b] < sm[b] - 1 || s1[b] > sm[b] + 1))
+            if (SW || m == 0)
+                bad_row |= sm[b] >= 0 ? (s1[b] >= 0 ? (s1[b] < sm[b] - 1 || s1[b] > sm[b] + 1)
+                                                    : (sm[b] > 1 && sm[b] < n - 2))
                                       : (s1[b] > 0 && s1[b] < n - 1);
+        }
+        // SW: the anchors of the springs destroyed in step m are the log's
+        // last entries, in (b, lane) order
+        v3<T> dA[B];
+        if constexpr (SW) {
+            bool gone[B], any = false;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                gone[b] = sm[b] >= 0 && s1[b] < 0;
+                dA[b] = zero3<T>();
+                any |= gone[b];
+            }
+            if (__ballot(any) != 0) {
+                const uint64_t below = (1ull << lane) - 1ull;
+                int64_t q0 = dcount;
+#pragma unroll
+                for (int b = 0; b < B; ++b) q0 -= __popcll(__ballot(gone[b]) & segm);
+                dcount = q0;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const uint64_t mk = __ballot(gone[b]) & segm;
+                    if (gone[b]) {
+                        const int64_t q = q0 + __popcll(mk & below);
+                        if (q >= 0 && q < a.dcap)
+                            dA[b] = dlog[q];
+                        else
+                            bad_row = true;
+                    }
+                    q0 += __popcll(mk);
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
             Rm[b] = R_pre[b];
             cr[b] = sm[b] < 0 && s1[b] >= 0;
             any_cr |= cr[b];
             Am[b] = zero3<T>();
             if (sm[b] >= 0) {
                 v3<double> Ap = Ac[b];
-                if (s1[b] < 0) {  // destroyed in step m: its advected anchor was written at row m + 1
-                    const v3<T> v = trajA[(int64_t)(m + 1) * a.total + off + li * B + b];
+                if (s1[b] < 0) {  // destroyed in step m: its advected anchor, stored by the forward or replay
+                    const v3<T> v = SW ? dA[b] : trajA[(int64_t)(m + 1) * a.total + off + li * B + b];
                     Ap = {(double)v.x, (double)v.y, (double)v.z};
                 }
                 const v3<T> At = {T(Ap.x), T(Ap.y), T(Ap.z)};
@@ -400,6 +447,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             p[5] = lA[b].z;
         }
     }
+    if constexpr (SW) bad_row |= dcount != 0;  // every logged destruction consumed
     if (bad_row) atomicOr(a.flags, kFlagReplay);
     // per-chain sums of the lane accumulators, in lane order
 #pragma unroll
@@ -418,7 +466,7 @@ template <typename T, int W, int B> hipError_t launch_t(const AdjointArgs& a, hi
     constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
     const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
     if (groups == 0) return hipSuccess;
-    if (a.check_moves)
+    if (a.stored)
         hipLaunchKernelGGL((k_adjoint<T, W, B, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
     else
         hipLaunchKernelGGL((k_adjoint<T, W, B, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);

@@ -315,8 +315,17 @@ int fail(ssp_handle* h, int code, const std::string& msg)
     } while (0)
 
 // ck_end (optional): where the last launch also writes the final state.
+// Outputs of a storing forward (see StepArgs).
+struct StoreOut {
+    void* traj = nullptr;
+    void* traj2 = nullptr;
+    void* dlog = nullptr;
+    int64_t* dcnt = nullptr;
+    int32_t dcap = 0;
+};
+
 int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, int8_t* rec_s = nullptr,
-                  int64_t rec_g0 = 0, const State* ck_end = nullptr, void* traj = nullptr, void* traj2 = nullptr)
+                  int64_t rec_g0 = 0, const State* ck_end = nullptr, const StoreOut* out = nullptr)
 {
     const ssp_config& k = h->res.cfg;
     const int64_t M = k.n_chains;
@@ -348,8 +357,13 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
             a.rec_s = rec_s;
             a.rec_g0 = rec_g0;
             if (ck_end && done + m == n) a.ck_end = *ck_end;
-            a.traj = traj;
-            a.traj2 = traj2;
+            if (out) {
+                a.traj = out->traj;
+                a.traj2 = out->traj2;
+                a.dlog = out->dlog;
+                a.dcnt = out->dcnt;
+                a.dcap = out->dcap;
+            }
             a.total = h->res.total_beads;
             HIPCHK(h, launch_step(k.precision, g.first.W, g.first.B, a, s));
         }
@@ -766,9 +780,27 @@ namespace {
 // Regions of a recording buffer: slot rows, checkpoints, replay state and
 // control words, segment trajectory, carried adjoint.
 struct RecLayout {
-    size_t rows, ckpts, scratch, ctrl, traj, traj2, lam, total;
+    size_t rows, ckpts, scratch, ctrl, traj, traj2, dlog, dcnt, lam, total;
     int n_seg;
+    int32_t dcap;  // stored window: destruction-log entries per chain
 };
+
+// Destruction-log capacity per chain for a stored window.  Destructions are
+// at most the initial springs (<= N) plus the creations; creations per step
+// have mean K 2 p_K <= 2 dt/(zeta_s N0) under either construction rule (each
+// of K attempts creates with probability 2 p_K, p_K = min{dt/(zeta_s N0 K),
+// 1/2}; or K attempts when p_K is clamped, K < 2 dt/(zeta_s N0)).  The
+// capacity adds 8 standard deviations of a Poisson count of that mean, plus
+// 16; a chain that still overflows is reported by ssp_adjoint.
+int32_t destruction_log_capacity(const ssp_handle* h, int64_t window)
+{
+    const ssp_config& k = h->res.cfg;
+    const double mean = (double)window * 2.0 * k.dt / (k.zeta_s * k.n0);
+    int32_t nmax = 0;
+    for (int32_t v : h->res.N) nmax = std::max(nmax, v);
+    const double cap = nmax + std::ceil(mean + 8.0 * std::sqrt(mean)) + 16.0;
+    return (int32_t)std::min(cap, 1.0e9);
+}
 
 RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
 {
@@ -787,8 +819,12 @@ RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
     L.ckpts = take((size_t)L.n_seg * h->lay.state_total);
     L.scratch = take(h->lay.state_total);
     L.ctrl = take(sizeof(int64_t) * kCtrlWords);
+    const bool store = L.n_seg == 1;  // the forward stores the window's trajectory
     L.traj = take((seg + 1) * beads * 3 * t);
-    L.traj2 = take((seg + 1) * beads * 3 * t);
+    L.traj2 = take((store ? 1 : seg + 1) * beads * 3 * t);
+    L.dcap = store ? destruction_log_capacity(h, window) : 0;
+    L.dlog = take((size_t)h->res.cfg.n_chains * (size_t)L.dcap * 3 * t);
+    L.dcnt = take(store ? sizeof(int64_t) * (size_t)h->res.cfg.n_chains : 0);
     L.lam = take(beads * 6 * t);
     L.total = o;
     return L;
@@ -836,13 +872,23 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
     // each segment's last launch writes the next checkpoint from its
     // epilogue, and the reverse pass replays each segment from its checkpoint.
     const bool store = R.n_seg == 1;
-    if (!store) HIPCHK(h, launch_copy_bytes(rec + R.ckpts, h->state, h->lay.state_total, s));
+    StoreOut so;
+    if (store) {
+        so.traj = rec + R.traj;
+        so.traj2 = rec + R.traj2;
+        so.dlog = rec + R.dlog;
+        so.dcnt = reinterpret_cast<int64_t*>(rec + R.dcnt);
+        so.dcap = R.dcap;
+        HIPCHK(h, launch_zero(reinterpret_cast<double*>(so.dcnt), h->res.cfg.n_chains, s));  // all-zero bits: 0
+    } else {
+        HIPCHK(h, launch_copy_bytes(rec + R.ckpts, h->state, h->lay.state_total, s));
+    }
     h->rec.ptr = nullptr;  // not a usable recording until the window is complete
     for (int c = 0; c < R.n_seg; ++c) {
         const int64_t m = std::min<int64_t>(ckpt_every, window - (int64_t)c * ckpt_every);
         const State next = state_at(h, rec + R.ckpts + (size_t)(c + 1) * h->lay.state_total);
         int rc = enqueue_steps(h, m, kappa_dev, s, rows, g0, c + 1 < R.n_seg ? &next : nullptr,
-                               store ? rec + R.traj : nullptr, store ? rec + R.traj2 : nullptr);
+                               store ? &so : nullptr);
         if (rc) return rc;
         const int64_t q = samples_between(h->steps, m, h->res.cfg.sample_every);
         h->steps += m;
@@ -926,7 +972,10 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             a.seed_lambda = (c == R.n_seg - 1) ? 1 : 0;
             a.init_terms = (c == 0 && init_window && h->rec.g0 == 0) ? 1 : 0;
             a.flags = h->flags();
-            a.check_moves = h->rec.stored ? 1 : 0;  // a replay checks the rows it re-creates
+            a.stored = h->rec.stored ? 1 : 0;  // a replay checks the rows it re-creates
+            a.dlog = rec + R.dlog;
+            a.dcnt = reinterpret_cast<const int64_t*>(rec + R.dcnt);
+            a.dcap = R.dcap;
             HIPCHK(h, launch_adjoint(k.precision, g.first.W, g.first.B, a, s));
         }
     }
@@ -935,6 +984,14 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
     uint32_t f = 0;
     HIPCHK(h, hipMemcpyAsync(&f, h->flags(), sizeof(f), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
+    if (f & kFlagLogOverflow) {
+        f &= ~(uint32_t)(kFlagLogOverflow | kFlagReplay);
+        HIPCHK(h, hipMemcpyAsync(h->flags(), &f, sizeof(f), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        return fail(h, SSP_ESIZE,
+                    "a chain destroyed more springs in the stored window than its log holds; gradients are "
+                    "invalid (record the window with checkpoints, ckpt_every < window)");
+    }
     if (f & kFlagReplay) {
         f &= ~(uint32_t)kFlagReplay;
         HIPCHK(h, hipMemcpyAsync(h->flags(), &f, sizeof(f), hipMemcpyHostToDevice, s));

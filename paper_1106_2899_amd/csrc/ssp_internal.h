@@ -18,7 +18,7 @@ constexpr int kMaxCorrLevels = 16;
 // ctrl[] words in the work buffer (device-resident so that captured graphs
 // can be replayed at any step count).
 enum CtrlWord { kCtrlSteps = 0, kCtrlCorrSamples = 1, kCtrlSeriesSamples = 2, kCtrlWords = 8 };
-enum FlagBits { kFlagNonFinite = 1u, kFlagSeriesOverflow = 2u, kFlagInternal = 4u, kFlagReplay = 8u };
+enum FlagBits { kFlagNonFinite = 1u, kFlagSeriesOverflow = 2u, kFlagInternal = 4u, kFlagReplay = 8u, kFlagLogOverflow = 16u };
 
 // Random-stream purposes (last counter word = step hi | purpose << 24).
 enum Purpose : uint32_t {
@@ -76,10 +76,21 @@ struct StepArgs {
     int64_t rec_g0;
     const int8_t* replay_s;  // [window+1][total], rows as rec_s: replay these slot states instead of deciding them
     int64_t total;         // beads (= slots) in the ensemble
-    // Replay output (with replay_s), rows 0..n_steps of the launch:
-    void* traj;            // [n_steps+1][total] T3: R at launch start and after every step
-    void* traj2;           // [n_steps+1][total] T3: A of every slot at row n_steps; at row m + 1 the
-                           // anchor of each spring destroyed in step m (as advected by that step); nothing else
+    // Trajectory output.  Replay (with replay_s), rows 0..n_steps of the launch:
+    //   traj  [n_steps+1][total] T3: R at launch start and after every step;
+    //   traj2 [n_steps+1][total] T3: A of every slot at row n_steps; at row m + 1 the anchor of each
+    //         spring destroyed in step m (as advected by that step); nothing else.
+    // Storing forward (traj set, no replay_s), rows counted from the window start (rec_g0):
+    //   traj  [window+1][total] T3: R as above;
+    //   traj2 [total] T3: A of every slot at the end of the launch;
+    //   dlog  [chains][dcap] T3: per chain, the anchor of each destroyed spring, in step order and
+    //         within a step in (bead-per-lane index, lane) order; dcnt [chains]: entries so far (a
+    //         count above dcap means the excess was not written).
+    void* traj;
+    void* traj2;
+    void* dlog;
+    int64_t* dcnt;
+    int32_t dcap;
 };
 
 struct AdjointArgs {
@@ -93,15 +104,20 @@ struct AdjointArgs {
     int64_t m0;             // window index of the segment start
     int32_t len;            // steps in the segment
     const void* traj;       // [len+1][total] T3: R (replay or storing-forward output)
-    const void* traj2;      // [len+1][total] T3: A at row len and of the springs destroyed in each step
+    const void* traj2;      // replay: [len+1][total] T3, A at row len and of the springs destroyed in each
+                            // step; stored window: [total] T3, A at the window end
+    const void* dlog;       // stored window: destroyed-spring anchors per chain (as StepArgs)
+    const int64_t* dcnt;    // stored window: log entries per chain
+    int32_t dcap;
     void* lam;              // [total][6] T: dJ/dR, dJ/dA carried between segments
     double* grad;           // [M][10]: dJ/dkappa (row-major), dJ/dN_s (accumulated)
-    uint32_t* flags;        // kFlagReplay: a recorded slot row out of range (read as empty) or an impossible move
+    uint32_t* flags;        // kFlagReplay: a recorded slot row out of range (read as empty), an impossible
+                            // move, or a destruction log that does not match the rows; kFlagLogOverflow
     int64_t total;
     int32_t comp;           // objective component 0..5 (xx yy zz xy yz zx)
     int32_t seed_lambda;    // 1 for the last segment: start from dJ/dR at its end
     int32_t init_terms;     // 1: include the N_s dependence of the sampled initial anchors (segment at window start)
-    int32_t check_moves;    // 1: check every pair of rows is a possible step (no replay has checked them)
+    int32_t stored;         // 1: a stored window (no replay has checked its rows; anchors from dlog)
 };
 
 struct CorrArgs {

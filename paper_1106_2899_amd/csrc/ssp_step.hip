@@ -138,7 +138,8 @@ template <typename T, int B> struct WaveLds {
 // probabilities); positions and anchors follow bit for bit.
 // ST: a recorded forward that also stores the trajectory the replay would
 // (positions every step, the anchors the adjoint cannot rebuild), so that the
-// reverse pass of a one-segment window needs no replay.
+// reverse pass of a one-segment window needs no replay.  Its destroyed-spring
+// anchors go to a compact per-chain log instead of a dense plane.
 template <typename T, int W, int B, bool K1, bool RP, bool ST>
 __device__ __forceinline__ void step_body(const StepArgs& a)
 {
@@ -268,9 +269,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     // first step), FP32 positions rounded from hi + lo.  Anchors are written
     // only where the adjoint cannot recover them by running the advection
     // backwards: for every slot at the launch end, and for each spring
-    // destroyed in a step, at that step's row.  A replay counts rows from its
-    // launch (one segment); a storing forward from the recorded window's
-    // start, however the window is split into launches.
+    // destroyed in a step (a replay: at that step's row; a storing forward:
+    // appended to the chain's log).  A replay counts rows from its launch (one
+    // segment); a storing forward from the recorded window's start, however
+    // the window is split into launches.
     constexpr bool kTraj = RP || ST;
     const int64_t trow0 = RP ? 0 : g0 - a.rec_g0;
     auto store_r = [&](int row) {
@@ -285,6 +287,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         reinterpret_cast<v3<T>*>(a.traj2)[(trow0 + row) * a.total + off + li * B + b] = ah[b] + al[b];
     };
     if constexpr (kTraj) store_r(0);
+    int64_t dcount = 0;  // storing forward: entries in this chain's destruction log
+    if constexpr (ST) dcount = valid ? a.dcnt[chain] : 0;
+    auto log_destroyed = [&](const bool (&destroyed)[B]) {
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < B; ++b) any |= destroyed[b];
+        if (!wave_any(any)) return;
+        const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const uint64_t m = __ballot(destroyed[b]) & seg_mask<W>(sb);
+            if (destroyed[b]) {
+                const int64_t q = dcount + __popcll(m & below);
+                if (q < a.dcap) reinterpret_cast<v3<T>*>(a.dlog)[(int64_t)chain * a.dcap + q] = ah[b] + al[b];
+            }
+            dcount += __popcll(m);
+        }
+    };
 
     bool finite_ok = true;
 
@@ -467,8 +487,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
                 }
                 if (j < n) {
                     const int v = replay_next[b];
-                    // a creation lands on an end; anything else moves by at most one bead
-                    const bool ok = s[b] >= 0 ? (v == -1 || (v >= s[b] - 1 && v <= s[b] + 1 && v < n))
+                    // a creation lands on an end; a destruction leaves an end after the hop, so
+                    // a bead within one of it; anything else moves by at most one bead
+                    const bool ok = s[b] >= 0 ? (v == -1 ? (s[b] <= 1 || s[b] >= n - 2)
+                                                         : (v >= s[b] - 1 && v <= s[b] + 1 && v < n))
                                               : (v == -1 || v == 0 || v == n - 1);
                     bad |= !ok;
                     s_rec[b] = ok ? v : s[b];
@@ -589,9 +611,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         }
         if constexpr (kTraj) {
             store_r(step + 1);
+            if constexpr (RP) {
 #pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (destroyed[b]) store_a(step + 1, b);
+                for (int b = 0; b < B; ++b)
+                    if (destroyed[b]) store_a(step + 1, b);
+            } else {
+                log_destroyed(destroyed);
+            }
         }
 
         // ---- observables of the new state.
@@ -682,10 +708,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
             }
         }
     }
-    if constexpr (kTraj) {
+    if constexpr (RP) {
 #pragma unroll
         for (int b = 0; b < B; ++b)
             if (li * B + b < n) store_a(a.n_steps, b);
+    }
+    if constexpr (ST) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (li * B + b < n) reinterpret_cast<v3<T>*>(a.traj2)[off + li * B + b] = ah[b] + al[b];
+        if (valid && li == 0) a.dcnt[chain] = dcount;
     }
     if (!finite_ok) atomicOr(a.flags, kFlagNonFinite);
 }

@@ -59,11 +59,15 @@ def test_adjoint_matches_oracle_shear(precision, rtol, ckpt):
     _check(got, want, rtol)
 
 
-def test_adjoint_matches_oracle_mixed_lengths_elongation_fp64():
+@pytest.mark.parametrize("ckpt", [50, 150], ids=["checkpointed", "stored"])
+def test_adjoint_matches_oracle_mixed_lengths_elongation_fp64(ckpt):
+    """Lengths 5..128 (one and two beads per lane): a stored window's
+    destruction log is read back in the (bead-per-lane, lane) order it was
+    written in."""
     N = [5, 16, 33, 70, 128, 9, 40, 100] * 3
     kap = np.diag([0.02, -0.01, -0.01])
-    e = _ens(N, precision="fp64", seed=9, corr_levels=0).init()
-    e.forward_record(150, 50, kap)
+    e = _ens(N, precision="fp64", seed=9, corr_levels=0, max_steps_per_launch=40).init()
+    e.forward_record(150, ckpt, kap)
     got = e.adjoint(component=0).cpu().numpy()
     want, _ = _oracle_grad(N, 9, 150, kap, 0)
     _check(got, want, 1e-9)
@@ -106,16 +110,16 @@ def test_autograd_function_matches_adjoint_means():
     np.testing.assert_allclose(J.detach().cpu().numpy(), o.stress()[:, 3].reshape(E, per).mean(axis=1), rtol=1e-10)
 
 
-@pytest.mark.parametrize("change", ["out_of_range", "impossible_move", "first_row"])
+@pytest.mark.parametrize("change", ["out_of_range", "impossible_move", "first_row", "inner_destruction"])
 @pytest.mark.parametrize("ckpt", [10, 40], ids=["checkpointed", "stored"])
 def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble(ckpt, change):
     """A slot row changed after ssp_forward_record is caught where the replay
     and the adjoint read it (both kernels check a row before using it, and read
     a bad entry as an empty slot): either a state that cannot exist (100 in a
     chain of N = 8), or one no step reaches from the row before (a spring that
-    appears in the middle of the chain), or a first row from which no step
-    reaches the second (which a replay, starting from its checkpoint, never
-    compares).  ssp_adjoint fails, the ensemble's own state is untouched, and a
+    appears in the middle of the chain, or vanishes more than one bead from an
+    end), or a first row from which no step reaches the second (which a
+    replay, starting from its checkpoint, never compares).  ssp_adjoint fails, the ensemble's own state is untouched, and a
     new recording differentiates normally."""
     from paper_1106_2899_amd._lib import SspError
 
@@ -134,6 +138,10 @@ def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble(ckpt, change
         empty = np.flatnonzero((r[19] == -1) & (r[20] == -1) & (r[21] == -1))
         assert empty.size > 0
         rows[20, int(empty[0])] = N // 2
+    elif change == "inner_destruction":
+        r = rows.cpu().numpy().astype(np.int8)
+        j = int(np.flatnonzero((r[19] >= 2) & (r[19] <= N - 3))[0])  # a spring away from the ends
+        rows[20:, j] = 255  # int8 -1: empty
     else:
         r = rows.cpu().numpy().astype(np.int8)
         j = int(np.flatnonzero((r[0] >= 0) & (r[1] >= 0))[0])  # a spring held over step 0

@@ -106,7 +106,7 @@ def test_polydisperse_full_size_sampled_chains():
 def test_differentiation_full_size_sampled_chains(stored):
     """All chains of the differentiation workload; the checkpointed window at
     its full length, and a 400-step window recorded as one stored segment
-    (about 42 GB of recording; the full 2000-step one, 210 GB, is timed by the
+    (about 22 GB of recording; the full 2000-step one, 110 GB, is timed by the
     benchmark)."""
     _need_gpu()
     from paper_1106_2899_amd.ensemble import Ensemble
