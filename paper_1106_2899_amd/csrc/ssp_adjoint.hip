@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
                                       : (s1[b] > 0 && s1[b] < n - 1);
         }
         // SW: the anchors of the springs destroyed in step m are the log's
-        // last entries, in (b, lane) order
+        // last entries, in slot order
         v3<T> dA[B];
         if constexpr (SW) {
             bool gone[B], any = false;
@@ -278,21 +278,24 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             }
             if (__ballot(any) != 0) {
                 const uint64_t below = (1ull << lane) - 1ull;
-                int64_t q0 = dcount;
-#pragma unroll
-                for (int b = 0; b < B; ++b) q0 -= __popcll(__ballot(gone[b]) & segm);
-                dcount = q0;
+                int tot = 0, lower = 0;
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const uint64_t mk = __ballot(gone[b]) & segm;
+                    tot += __popcll(mk);
+                    lower += __popcll(mk & below);
+                }
+                dcount -= tot;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
                     if (gone[b]) {
-                        const int64_t q = q0 + __popcll(mk & below);
+                        const int64_t q = dcount + lower;
                         if (q >= 0 && q < a.dcap)
                             dA[b] = dlog[q];
                         else
                             bad_row = true;
+                        ++lower;
                     }
-                    q0 += __popcll(mk);
                 }
             }
         }

@@ -84,8 +84,8 @@ struct StepArgs {
     //   traj  [window+1][total] T3: R as above;
     //   traj2 [total] T3: A of every slot at the end of the launch;
     //   dlog  [chains][dcap] T3: per chain, the anchor of each destroyed spring, in step order and
-    //         within a step in (bead-per-lane index, lane) order; dcnt [chains]: entries so far (a
-    //         count above dcap means the excess was not written).
+    //         within a step in slot order (the same for every mapping); dcnt [chains]: entries so
+    //         far (a count above dcap means the excess was not written).
     void* traj;
     void* traj2;
     void* dlog;

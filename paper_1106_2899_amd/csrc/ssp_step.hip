@@ -294,16 +294,25 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
 #pragma unroll
         for (int b = 0; b < B; ++b) any |= destroyed[b];
         if (!wave_any(any)) return;
+        // entries of one step in slot order (slot li B + b), whatever the mapping:
+        // a slot's rank counts the destroyed slots of lower lanes and its own lower b
         const uint64_t below = (1ull << lane) - 1ull;
+        int tot = 0, lower = 0;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const uint64_t m = __ballot(destroyed[b]) & seg_mask<W>(sb);
-            if (destroyed[b]) {
-                const int64_t q = dcount + __popcll(m & below);
-                if (q < a.dcap) reinterpret_cast<v3<T>*>(a.dlog)[(int64_t)chain * a.dcap + q] = ah[b] + al[b];
-            }
-            dcount += __popcll(m);
+            tot += __popcll(m);
+            lower += __popcll(m & below);
         }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (destroyed[b]) {
+                const int64_t q = dcount + lower;
+                if (q < a.dcap) reinterpret_cast<v3<T>*>(a.dlog)[(int64_t)chain * a.dcap + q] = ah[b] + al[b];
+                ++lower;
+            }
+        }
+        dcount += tot;
     };
 
     bool finite_ok = true;

@@ -62,8 +62,7 @@ def test_adjoint_matches_oracle_shear(precision, rtol, ckpt):
 @pytest.mark.parametrize("ckpt", [50, 150], ids=["checkpointed", "stored"])
 def test_adjoint_matches_oracle_mixed_lengths_elongation_fp64(ckpt):
     """Lengths 5..128 (one and two beads per lane): a stored window's
-    destruction log is read back in the (bead-per-lane, lane) order it was
-    written in."""
+    destruction log is read back in the slot order it was written in."""
     N = [5, 16, 33, 70, 128, 9, 40, 100] * 3
     kap = np.diag([0.02, -0.01, -0.01])
     e = _ens(N, precision="fp64", seed=9, corr_levels=0, max_steps_per_launch=40).init()
@@ -171,6 +170,30 @@ def test_stored_window_gives_the_checkpointed_gradients(precision):
         e.forward_record(T, ckpt, kap)
         got[ckpt] = e.adjoint(component=3).cpu().numpy()
     _check(got[T], got[50], 1e-12 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_stored_window_survives_a_mapping_change(precision, rtol):
+    """A stored window's destruction log is in slot order, which every mapping
+    shares: recorded at 32 lanes x 1 bead and differentiated at 16 x 2, it
+    gives the gradients of the unchanged mapping (up to the order of the FP64
+    sums).  The window holds steps in which one chain loses several springs,
+    where the order matters."""
+    N, M, T = 24, 64, 400
+    kap = _shear(0.3)
+    got = []
+    for remap in (False, True):
+        e = _ens(N, M, precision=precision, seed=13, corr_levels=0).init()
+        e.set_mapping(2, 32, 32, 1)
+        e.forward_record(T, T, kap)
+        if remap:
+            off = e._rec_p - e._rec_t.data_ptr()
+            rows = e._rec_t[off:off + (T + 1) * N * M].view(T + 1, M, N).cpu().numpy().astype(np.int8)
+            gone = (rows[:-1] >= 0) & (rows[1:] < 0)
+            assert (gone.sum(axis=2) >= 2).any()
+            e.set_mapping(2, 32, 16, 2)
+        got.append(e.adjoint(component=3).cpu().numpy())
+    _check(got[1], got[0], rtol)
 
 
 @pytest.mark.parametrize("ckpt", [48, 200], ids=["checkpointed", "stored"])
