@@ -578,3 +578,31 @@ def test_reconstruction_only_at_ends_and_capacity():
         assert np.all(e.S[destroyed] == -1)
         prev = e.S.copy()
     assert np.all(e.S < 6)
+
+
+@pytest.mark.parametrize("rule", [0, 1], ids=["k_equals_c_minus_z", "k_equals_1"])
+def test_destructions_per_window_stay_within_the_stored_log_capacity(rule):
+    """A stored window logs the anchor of every destroyed spring, up to
+    N + ceil(mu + 8 sqrt(mu)) + 16 entries per chain with mu = window 2 dt /
+    (zeta_s N0).  The bound rests on two facts checked here on the oracle's
+    own runs (Sec. 3.2 reconstruction step): each destruction ends a spring
+    present at the window start or created in it, and the creations per chain
+    and step have mean K 2 p_K <= 2 dt / (zeta_s N0) under either rule."""
+    N, M, T = 16, 256, 2000
+    o = oracle.Ensemble([N] * M, seed=41, construct_rule=rule).init()
+    S0 = o.S.reshape(M, N).copy()
+    created = np.zeros(M, dtype=np.int64)
+    gone = np.zeros(M, dtype=np.int64)
+    prev = S0
+    for _ in range(T):
+        o.step()
+        cur = o.S.reshape(M, N)
+        created += ((prev < 0) & (cur >= 0)).sum(axis=1)
+        gone += ((prev >= 0) & (cur < 0)).sum(axis=1)
+        prev = cur.copy()
+    mu = T * 2.0 * o.dt / (o.zeta_s * o.n0)
+    # conservation: springs at the end = at the start + created - destroyed
+    assert np.array_equal((prev >= 0).sum(axis=1), (S0 >= 0).sum(axis=1) + created - gone)
+    # the mean creation count is at most mu (5 standard errors of a Poisson mean)
+    assert created.mean() <= mu + 5.0 * math.sqrt(mu / M)
+    assert gone.max() <= N + math.ceil(mu + 8.0 * math.sqrt(mu)) + 16
