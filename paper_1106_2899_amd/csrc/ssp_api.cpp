@@ -780,7 +780,7 @@ namespace {
 // Regions of a recording buffer: slot rows, checkpoints, replay state and
 // control words, segment trajectory, carried adjoint.
 struct RecLayout {
-    size_t rows, ckpts, scratch, ctrl, traj, traj2, dlog, dcnt, lam, total;
+    size_t rows, ckpts, ctrl, traj, traj2, dlog, dcnt, lam, total;
     int n_seg;
     int32_t dcap;  // stored window: destruction-log entries per chain
 };
@@ -817,7 +817,6 @@ RecLayout rec_layout(const ssp_handle* h, int64_t window, int32_t ckpt)
     };
     L.rows = take((size_t)(window + 1) * beads);
     L.ckpts = take((size_t)L.n_seg * h->lay.state_total);
-    L.scratch = take(h->lay.state_total);
     L.ctrl = take(sizeof(int64_t) * kCtrlWords);
     const bool store = L.n_seg == 1;  // the forward stores the window's trajectory
     L.traj = take((seg + 1) * beads * 3 * t);
@@ -916,20 +915,18 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
     const RecLayout R = rec_layout(h, h->rec.window, h->rec.ckpt);
     char* rec = static_cast<char*>(const_cast<void*>(rec_dev));
     const int8_t* rows = reinterpret_cast<const int8_t*>(rec + R.rows);
-    char* scratch = rec + R.scratch;
     int64_t* sctrl = reinterpret_cast<int64_t*>(rec + R.ctrl);
     HIPCHK(h, launch_zero(grad_dev, k.n_chains * 10, s));
     for (int c = R.n_seg - 1; c >= 0; --c) {
         const int64_t m = std::min<int64_t>(h->rec.ckpt, h->rec.window - (int64_t)c * h->rec.ckpt);
-        // replay the segment from its checkpoint, storing the trajectory
-        // (a one-segment window has it from the forward)
+        // replay the segment from its checkpoint (read in place, left as it
+        // is), storing the trajectory; a one-segment window has it from the
+        // forward
         if (!h->rec.stored) {
-            HIPCHK(h, launch_copy_bytes(scratch, rec + R.ckpts + (size_t)c * h->lay.state_total,
-                                        h->lay.state_total, s));
             HIPCHK(h, launch_set_ctrl_steps(sctrl, h->rec.g0 + (int64_t)c * h->rec.ckpt, s));
             for (auto& g : h->groups) {
                 StepArgs a{};
-                a.st = state_at(h, scratch);
+                a.st = state_at(h, rec + R.ckpts + (size_t)c * h->lay.state_total);  // read in place
                 a.ct = h->ct();
                 a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
                 a.n_tasks = g.second.second;
@@ -979,8 +976,9 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
             HIPCHK(h, launch_adjoint(k.precision, g.first.W, g.first.B, a, s));
         }
     }
-    // A bad recording leaves the ensemble itself untouched (the replay runs on
-    // a scratch copy): report it and clear its flag.
+    // A bad recording leaves the ensemble itself untouched (the replay starts
+    // from a checkpoint and writes only the trajectory): report it and clear
+    // its flag.
     uint32_t f = 0;
     HIPCHK(h, hipMemcpyAsync(&f, h->flags(), sizeof(f), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));

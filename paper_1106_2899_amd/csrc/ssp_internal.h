@@ -55,7 +55,7 @@ struct Physics {
 };
 
 struct StepArgs {
-    State st;
+    State st;  // read at launch start, written back at the end (a replay only reads it)
     ChainTables ct;
     const int32_t* tasks;  // chains handled by this launch, one per segment
     int64_t n_tasks;

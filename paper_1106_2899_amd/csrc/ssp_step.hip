@@ -686,23 +686,28 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         if (a.sample_every > 0) phase = (phase + 1 == a.sample_every) ? 0 : phase + 1;
     }
 
+    // The final state goes back to the state buffer, except from a replay,
+    // which reads its checkpoint in place and leaves it for later reverse
+    // passes (its output is the trajectory).
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int i = li * B + b;
         if (i < n) {
             finite_ok &= finite3(rh[b]);
-            st3<T>(a.st.r0, off + i, rh[b]);
-            st3<T>(a.st.a0, off + i, ah[b]);
-            if constexpr (kComp) {
-                st3<T>(a.st.r1, off + i, rl[b]);
-                st3<T>(a.st.a1, off + i, al[b]);
+            if constexpr (!RP) {
+                st3<T>(a.st.r0, off + i, rh[b]);
+                st3<T>(a.st.a0, off + i, ah[b]);
+                if constexpr (kComp) {
+                    st3<T>(a.st.r1, off + i, rl[b]);
+                    st3<T>(a.st.a1, off + i, al[b]);
+                }
+                a.st.s[off + i] = s[b];
             }
-            a.st.s[off + i] = s[b];
         }
     }
     // a second copy of the final state when asked (the next checkpoint of a
     // recorded window)
-    if (a.ck_end.r0) {
+    if (!RP && a.ck_end.r0) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;

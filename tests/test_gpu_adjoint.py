@@ -172,6 +172,24 @@ def test_stored_window_gives_the_checkpointed_gradients(precision):
     _check(got[T], got[50], 1e-12 if precision == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("ckpt", [40, 200], ids=["checkpointed", "stored"])
+def test_reverse_pass_leaves_the_recording_intact(ckpt):
+    """The replay reads each checkpoint in place and writes only the
+    trajectory, so a second reverse pass over the same recording (here after
+    one for another component) gives bitwise the same gradients, and the
+    ensemble's own state is untouched."""
+    N, M, T = 12, 32, 200
+    kap = _shear(0.2)
+    e = _ens(N, M, precision="fp32", seed=17, corr_levels=0).init()
+    e.forward_record(T, ckpt, kap)
+    state = [x.clone() for x in e.state()]
+    g1 = e.adjoint(component=3).cpu().numpy()
+    e.adjoint(component=0)
+    g2 = e.adjoint(component=3).cpu().numpy()
+    assert np.array_equal(g1, g2)
+    assert all(torch.equal(x, y) for x, y in zip(state, e.state()))
+
+
 @pytest.mark.parametrize("precision,rtol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_stored_window_survives_a_mapping_change(precision, rtol):
     """A stored window's destruction log is in slot order, which every mapping
