@@ -121,9 +121,11 @@ template <typename T> __device__ __forceinline__ bool finite3(v3<T> v)
 // Wave-private LDS: the bead records double as the transpose buffer of the
 // stress sums ([64 lanes][12] FP64), which is used only after the records of
 // a step have been consumed.
-template <typename T, int B> struct WaveLds {
+// SAMP: room for the stress-sample partials (a replay samples nothing, and
+// without them its LDS no longer limits the waves per SIMD).
+template <typename T, int B, bool SAMP> struct WaveLds {
     static constexpr int kRecBytes = (int)sizeof(BeadRec<T>) * kWaveSize * B;
-    static constexpr int kSumBytes = (int)sizeof(double) * kWaveSize * kSampleValues;
+    static constexpr int kSumBytes = SAMP ? (int)sizeof(double) * kWaveSize * kSampleValues : 0;
     static constexpr int kShared = kRecBytes > kSumBytes ? kRecBytes : kSumBytes;
     alignas(16) unsigned char shared[kShared];
     Off4<T> off[kWaveSize * B];
@@ -147,7 +149,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     constexpr int kChainsPerWave = kWaveSize / W;
     constexpr int kCap = W * B;  // bead capacity of a segment
 
-    __shared__ WaveLds<T, B> lds[kWavesPerGroup];
+    __shared__ WaveLds<T, B, !RP> lds[kWavesPerGroup];
     // creation thresholds for p_K and 2 p_K, K = 0..kMaxBeads, read every step
     __shared__ uint32_t thr[2 * (kMaxBeads + 1)];
     for (int q = threadIdx.x; q < 2 * (kMaxBeads + 1); q += kGroupThreads) thr[q] = a.thr[q];
@@ -756,10 +758,12 @@ k_step(StepArgs a)
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
-// segment's trajectory this way).  It samples no stress, so without the
-// sampling code its registers fit 5 waves per SIMD with no spills.
+// segment's trajectory this way).  It samples no stress: without the sampling
+// code and its LDS partials, FP32 with one bead per lane fits 6 waves per SIMD
+// (79 VGPRs, 17 KB of LDS per group) with no spills.
 template <typename T, int W, int B>
-__global__ void __launch_bounds__(kGroupThreads) k_replay(StepArgs a)
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && B == 1 ? 6 : 1)))
+k_replay(StepArgs a)
 {
     step_body<T, W, B, false, true, false>(a);
 }
