@@ -172,6 +172,41 @@ def test_stored_window_gives_the_checkpointed_gradients(precision):
     _check(got[T], got[50], 1e-12 if precision == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("ckpt", [7, 30], ids=["checkpointed", "stored"])
+def test_adjoint_edge_cases_fp64(ckpt):
+    """N = 2 chains (both beads are ends), a ragged launch (five N = 128
+    chains: the second group holds one; seven N = 8 chains: a wave partly
+    filled), a window that starts at an odd step after 3 plain steps (so no
+    initial-anchor term), and a last segment shorter than the others
+    (30 = 4 x 7 + 2)."""
+    lengths = [2] * 3 + [128] * 5 + [8] * 7
+    kap = _shear(0.2)
+    e = _ens(np.array(lengths), precision="fp64", seed=27, corr_levels=0).init()
+    e.step(3, kap)
+    e.forward_record(30, ckpt, kap)
+    got = e.adjoint(component=3).cpu().numpy()
+    o = oracle.Ensemble(lengths, seed=27).init()
+    for _ in range(3):
+        o.step(kap)
+    Rt, At, St = o.run_record(30, kap)
+    gk, gns = o.adjoint(Rt, At, St, kap, step0=3, comp=3, init_window=False)
+    want = np.concatenate([gk.reshape(len(lengths), 9), gns[:, None]], axis=1)
+    assert np.array_equal(e.state()[2].cpu().numpy(), o.S)
+    _check(got, want, 1e-9)
+
+
+@pytest.mark.parametrize("ckpt", [1, 4], ids=["checkpointed", "stored"])
+def test_one_step_window_fp64(ckpt):
+    """The shortest window: one step, as one checkpoint segment or stored."""
+    N, M = 10, 16
+    kap = _shear(0.5)
+    e = _ens(N, M, precision="fp64", seed=29, corr_levels=0).init()
+    e.forward_record(1, ckpt, kap)
+    got = e.adjoint(component=3).cpu().numpy()
+    want, _ = _oracle_grad([N] * M, 29, 1, kap, 3)
+    _check(got, want, 1e-9)
+
+
 @pytest.mark.parametrize("ckpt", [40, 200], ids=["checkpointed", "stored"])
 def test_reverse_pass_leaves_the_recording_intact(ckpt):
     """The replay reads each checkpoint in place and writes only the
