@@ -11,7 +11,8 @@ resident in HBM before the timed region.
 
 Printed: one JSON line with bead-steps/s of the batched FP32 path, the plain
 FP64 path at the same shape, the VALU roofline of the step kernel (measured
-with HIP events on the launch stream), the adjoint/forward time ratio, the
+with HIP events on the launch stream), the adjoint/forward time ratio (a
+checkpoint every 100 steps, and the window stored as one segment), the
 batched FP32 path on the start-up shear and polydisperse workloads (context),
 and the FP64 CPU oracle timed on the host cores on a bounded sample.
 """
