@@ -282,7 +282,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
-            if (i < n) reinterpret_cast<v3<T>*>(a.traj)[e + i] = rh[b] + rl[b];
+            if (i < n) {  // streamed out once, read back once by the adjoint: non-temporal
+                const v3<T> v = rh[b] + rl[b];
+                T* q = reinterpret_cast<T*>(a.traj) + 3 * (e + i);
+                __builtin_nontemporal_store(v.x, q);
+                __builtin_nontemporal_store(v.y, q + 1);
+                __builtin_nontemporal_store(v.z, q + 2);
+            }
         }
     };
     auto store_a = [&](int row, int b) {
