@@ -288,6 +288,15 @@ int ssp_destroy(ssp_handle* h);
 /* Message for the last error on h (NULL: last create/query error). */
 const char* ssp_last_error(const ssp_handle* h);
 
+/* Warning about a configuration that is accepted but leaves the regime the
+ * step map of Sec. 3.1 is written for, or NULL when there is none: with
+ * dt / zeta_s > 1/4 the 1/2 caps on the hop probabilities can bind (and, for
+ * larger ratios, those on construction and destruction), so the step no
+ * longer follows the continuous-time hop rates it discretises.  h: the
+ * handle's configuration; NULL: the configuration of the last ssp_query_sizes
+ * or ssp_create on the calling thread.  The string is owned by the library. */
+const char* ssp_warning(const ssp_handle* h);
+
 #ifdef __cplusplus
 }
 #endif

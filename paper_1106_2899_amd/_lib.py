@@ -45,6 +45,7 @@ EXPORTS = [
     "ssp_kernel_time",
     "ssp_destroy",
     "ssp_last_error",
+    "ssp_warning",
 ]
 
 
@@ -119,11 +120,12 @@ def lib():
             "ssp_kernel_time": [vp, f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
             "ssp_destroy": [vp],
             "ssp_last_error": [vp],
+            "ssp_warning": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = ctypes.c_char_p if name == "ssp_last_error" else ctypes.c_int
+            f.restype = ctypes.c_char_p if name in ("ssp_last_error", "ssp_warning") else ctypes.c_int
         _lib = L
     return _lib
 

@@ -21,6 +21,25 @@ using namespace ssp;
 namespace {
 
 thread_local std::string g_create_error;
+thread_local std::string g_create_warning;
+
+// Sec. 3.1 caps the hop probabilities at 1/2, the construction probability
+// per attempt at 1/2 and the destruction probability at 1; at dt / zeta_s =
+// 0.1 (Sec. 4.1) none of them binds.  Above dt / zeta_s = 1/4 a hop
+// probability 2 (dt / zeta_s) / (1 + e^{2 q y}) can reach 1/2 for y < 0, and
+// the step no longer follows the continuous-time rates it discretises: a
+// configuration that large is accepted, with a warning.
+std::string cap_warning(const ssp_config& k)
+{
+    const double h = k.dt / k.zeta_s;
+    if (!(h > 0.25)) return std::string();
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "dt/zeta_s = %.4g > 0.25: the 1/2 caps on the hop probabilities%s%s bind (Sec. 3.1 step map)", h,
+                  (h / k.n0 > 0.5) ? ", the construction probability" : "",
+                  (h >= 1.0) ? " and the destruction probability" : "");
+    return std::string(buf);
+}
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -255,6 +274,7 @@ struct ssp_handle {
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int64_t, const double*>, hipGraphExec_t> graphs;
     std::string err;
+    std::string warning;  // set at creation (cap_warning)
     // kernel timing mode: events bracket every step-kernel launch
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -481,7 +501,9 @@ int ssp_config_init(ssp_config* c)
 int ssp_query_sizes(const ssp_config* cfg, size_t* state_bytes, size_t* work_bytes)
 {
     Resolved r;
+    g_create_warning.clear();
     if (!resolve(cfg, r, g_create_error)) return SSP_EINVAL;
+    g_create_warning = cap_warning(r.cfg);
     if (cfg->corr_levels > 0 && cfg->corr_batches > cfg->n_chains) {
         g_create_error = "corr_batches exceeds n_chains";
         return SSP_EINVAL;
@@ -516,6 +538,8 @@ int ssp_create(const ssp_config* cfg, void* state_dev, void* work_dev, ssp_handl
         delete h;
         return SSP_EINVAL;
     }
+    h->warning = cap_warning(h->res.cfg);
+    g_create_warning = h->warning;
     h->res.cfg.n_beads_host = nullptr;
     h->res.cfg.element_offsets_host = nullptr;
     h->res.cfg.chain_ids_host = nullptr;
@@ -1066,5 +1090,11 @@ int ssp_destroy(ssp_handle* h)
 }
 
 const char* ssp_last_error(const ssp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+const char* ssp_warning(const ssp_handle* h)
+{
+    const std::string& w = h ? h->warning : g_create_warning;
+    return w.empty() ? nullptr : w.c_str();
+}
 
 }  // extern "C"

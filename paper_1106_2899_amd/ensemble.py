@@ -6,6 +6,7 @@ in the HIP library behind the C ABI of include/ssp.h.
 from __future__ import annotations
 
 import ctypes
+import warnings
 from typing import Optional, Sequence, Union
 
 import numpy as np
@@ -105,6 +106,9 @@ class Ensemble:
         self.series_capacity = cfg.series_capacity
         sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
         check(L.ssp_query_sizes(ctypes.byref(cfg), ctypes.byref(sb), ctypes.byref(wb)))
+        msg = L.ssp_warning(None)
+        if msg:
+            warnings.warn(msg.decode(), stacklevel=2)
         self.state_bytes, self.work_bytes = sb.value, wb.value
         with torch.cuda.device(self.device):
             self._state_t, self._state_p = _aligned_buffer(sb.value, self.device)

@@ -115,3 +115,22 @@ def test_product_path_does_not_reference_the_oracle():
                 with open(os.path.join(dp, fn)) as f:
                     src = f.read()
                 assert "import oracle" not in src and "ssp_oracle" not in src, fn
+
+
+@pytest.mark.parametrize("zeta_s,n0,want", [
+    (0.1, 4.0, None),                                    # the paper's dt / zeta_s = 0.1: no cap binds
+    (0.04, 4.0, None),                                   # 0.25 exactly: still below
+    (0.02, 4.0, "hop probabilities bind"),               # 0.5
+    (0.0025, 1.0, "construction probability and the destruction"),  # 4: every cap can bind
+])
+def test_warning_when_the_half_caps_can_bind(zeta_s, n0, want):
+    """dt / zeta_s > 1/4 is accepted with a warning naming the caps of the
+    Sec. 3.1 step map that can bind; none at the paper's parameters."""
+    L = _lib()
+    rc, *_ = _query(L, _cfg(L, n_chains=8, n_beads=8, corr_batches=4, zeta_s=zeta_s, n0=n0))
+    assert rc == 0
+    msg = L.lib().ssp_warning(None)
+    if want is None:
+        assert msg is None
+    else:
+        assert msg is not None and want in msg.decode() and "dt/zeta_s" in msg.decode(), msg

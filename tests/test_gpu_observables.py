@@ -12,6 +12,8 @@ import pytest
 
 import oracle
 
+from _corr import oracle_G
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -62,18 +64,25 @@ def test_chunking_and_graph_invariance_bitwise():
         assert torch.equal(x, y)
 
 
-def test_correlator_matches_oracle_fp64():
-    M, N, every, steps, L = 32, 8, 3, 3000, 10
-    e = _ens(N, M, precision="fp64", seed=6, sample_every=every, corr_levels=L, corr_batches=4).init()
+@pytest.mark.parametrize("M,batches", [(32, 4), (100, 7)])
+def test_correlator_and_batch_means_error_match_oracle_fp64(M, batches):
+    """G(t) and its batch-means error G_err (standard error of the means of
+    `batches` contiguous equal chain groups; 100 chains in 7 groups makes the
+    groups unequal) against the same definitions applied to the oracle's
+    samples of the same chains."""
+    N, every, steps, L = 8, 3, 3000, 10
+    e = _ens(N, M, precision="fp64", seed=6, sample_every=every, corr_levels=L, corr_batches=batches).init()
     e.step(steps)
     got = e.correlator()
     o = oracle.Ensemble([N] * M, seed=6).init()
     s = o.run(steps, sample_every=every)
-    G, cnt = _oracle_G(s, L)
+    G, G_err, cnt = oracle_G(s, L, batches=batches)
     assert np.array_equal(got["counts"], cnt)
     np.testing.assert_allclose(got["G"], G, rtol=1e-9, atol=1e-11)
     np.testing.assert_allclose(got["tau"][0], np.arange(16) * every * 0.01)
-    assert np.all(got["G_err"][cnt > 0] >= 0)
+    ok = cnt > 1
+    assert np.all(G_err[ok] > 0)
+    np.testing.assert_allclose(got["G_err"], G_err, rtol=1e-8, atol=1e-12)
 
 
 def test_virtual_stress_channel_matches_oracle_fp64():
