@@ -132,6 +132,14 @@ int ssp_step(ssp_handle* h, int64_t n_steps, const double* kappa_dev, ssp_stream
  * SSP_ENONFINITE if the non-finite flag is set. */
 int ssp_read_stress(ssp_handle* h, double* out_dev, ssp_stream stream);
 
+/* Ensemble average of the stress within every fluid element, out_dev:
+ * [E][12] FP64, out[e][c] = (1/M_e) sum over the chains of element e of the
+ * per-chain value c of ssp_read_stress (sigma, then sigma^v; Sec. 2.1 stress
+ * equation, Appendix B), Neumaier-compensated in a fixed order.  Uses the
+ * handle's sample staging area, which holds nothing between steps.
+ * Synchronises the stream; SSP_ENONFINITE as ssp_read_stress. */
+int ssp_read_element_stress(ssp_handle* h, double* out_dev, ssp_stream stream);
+
 /* Canonical FP64 view of the state: R_dev [sum N][3], A_dev [sum N][3]
  * (hi + lo for the FP32 path), S_dev [sum N] int32 (bead index 0..N-1, or
  * -1 for an empty slot; the anchor of an empty slot is meaningless).
@@ -167,13 +175,15 @@ int ssp_read_correlator(ssp_handle* h, double* G_dev, double* G_err_dev, double*
 /* The virtual-stress channel of the correlator (config corr_virtual = 1):
  * Gv(t) = <sigma^v_ab(t) [sigma_ab + sigma^v_ab](t0)> per chain in kBT units,
  * averaged over ab in {xy, yz, zx}, on the same multiple-tau grid, counts and
- * batch-means errors as ssp_read_correlator.  Gv(t) / G(t) is the relative
- * contribution of the virtual stress to the shear relaxation modulus of
- * Sec. 4.1 (its numerator <sigma^v(t) sigma> + <sigma^v(t) sigma^v> over the
- * denominator <sigma(t) sigma> + <sigma(t) sigma^v>).  Gv_dev, Gv_err_dev:
- * [corr_levels][16] FP64 (device).  Synchronises the stream.  SSP_ESTATE when
+ * batch-means errors as ssp_read_correlator.  dGv(t) = Gv(t) / G(t) is the
+ * relative contribution of the virtual stress to the shear relaxation modulus
+ * of Sec. 4.1 (its numerator <sigma^v(t) sigma> + <sigma^v(t) sigma^v> over
+ * the denominator <sigma(t) sigma> + <sigma(t) sigma^v>), NaN at lags without
+ * data or where G = 0.  Gv_dev, Gv_err_dev, dGv_dev: [corr_levels][16] FP64
+ * (device); dGv_dev may be NULL.  Synchronises the stream.  SSP_ESTATE when
  * the channel is off. */
-int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_dev, ssp_stream stream);
+int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_dev, double* dGv_dev,
+                                ssp_stream stream);
 
 /* Linear viscoelasticity from the relaxation modulus (the relations of
  * Sec. 4.1): G'(w) = w int G(t) sin(w t) dt, G''(w) = w int G(t) cos(w t) dt,
@@ -261,6 +271,18 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
  * fails with SSP_ESIZE; record such a window with checkpoints. */
 int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
                 double* grad_dev, ssp_stream stream);
+
+/* The reverse pass of ssp_adjoint reduced per fluid element: elem_grad_dev
+ * [E][10] FP64 receives the ensemble averages over the chains of each element
+ * of dJ_k/dkappa_ab (9, row-major) and dJ_k/dN_s, i.e. the gradients of the
+ * element's mean final stress component (1/M_e) sum_k sigma_component,k, each
+ * a Neumaier-compensated sum in a fixed order divided by M_e.
+ * chain_grad_dev [M][10] FP64 is the caller's workspace for the per-chain
+ * gradients and holds them on return (as ssp_adjoint's grad_dev).  Other
+ * arguments, synchronisation and errors as ssp_adjoint; on an error
+ * elem_grad_dev is not written. */
+int ssp_adjoint_elements(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component,
+                         int32_t init_window, double* chain_grad_dev, double* elem_grad_dev, ssp_stream stream);
 
 /* Chain-to-wavefront mapping for the chains with n_lo <= N <= n_hi: each
  * such chain occupies lanes_per_chain lanes (8, 16, 32 or 64) with

@@ -28,6 +28,7 @@ EXPORTS = [
     "ssp_init_equilibrium",
     "ssp_step",
     "ssp_read_stress",
+    "ssp_read_element_stress",
     "ssp_read_state",
     "ssp_write_state",
     "ssp_read_element_series",
@@ -40,6 +41,7 @@ EXPORTS = [
     "ssp_adjoint_bytes",
     "ssp_forward_record",
     "ssp_adjoint",
+    "ssp_adjoint_elements",
     "ssp_set_mapping",
     "ssp_set_kernel_timing",
     "ssp_kernel_time",
@@ -103,11 +105,12 @@ def lib():
             "ssp_init_equilibrium": [vp, vp],
             "ssp_step": [vp, i64, vp, vp],
             "ssp_read_stress": [vp, vp, vp],
+            "ssp_read_element_stress": [vp, vp, vp],
             "ssp_read_state": [vp, vp, vp, vp, vp],
             "ssp_write_state": [vp, vp, vp, vp, vp],
             "ssp_read_element_series": [vp, vp, ctypes.POINTER(ctypes.c_int64), vp],
             "ssp_read_correlator": [vp, vp, vp, f64p, ctypes.POINTER(ctypes.c_int64), vp],
-            "ssp_read_correlator_virtual": [vp, vp, vp, vp],
+            "ssp_read_correlator_virtual": [vp, vp, vp, vp, vp],
             "ssp_linear_viscoelasticity": [vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, vp, vp, vp],
             "ssp_reset_observables": [vp, vp],
             "ssp_step_count": [vp, ctypes.POINTER(ctypes.c_int64)],
@@ -115,6 +118,7 @@ def lib():
             "ssp_adjoint_bytes": [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
             "ssp_forward_record": [vp, i64, i32, vp, vp, vp],
             "ssp_adjoint": [vp, vp, vp, i32, i32, vp, vp],
+            "ssp_adjoint_elements": [vp, vp, vp, i32, i32, vp, vp, vp],
             "ssp_set_mapping": [vp, i32, i32, i32, i32],
             "ssp_set_kernel_timing": [vp, ctypes.c_int],
             "ssp_kernel_time": [vp, f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],

@@ -34,15 +34,8 @@ class FinalStress(torch.autograd.Function):
         kappa = (r[:, None, None] * dirs).reshape(ensemble.n_elements, 9).contiguous()
         comp = COMPONENTS[component] if isinstance(component, str) else int(component)
         ensemble.forward_record(window, ckpt_every, kappa)
-        sig = ensemble.stress()[:, comp]
-        offs = torch.as_tensor(ensemble.element_offsets, dtype=torch.int64)
-        counts = (offs[1:] - offs[:-1]).to(ensemble.device)
-        elem = torch.repeat_interleave(torch.arange(ensemble.n_elements, device=ensemble.device), counts)
-        J = torch.zeros(ensemble.n_elements, dtype=torch.float64, device=ensemble.device)
-        J.index_add_(0, elem, sig)
-        J = J / counts
+        J = ensemble.element_stress()[:, comp].contiguous()  # element means (library reduction)
         ctx.ensemble, ctx.dirs, ctx.comp, ctx.init_window = ensemble, dirs, comp, init_window
-        ctx.elem, ctx.counts = elem, counts
         ctx.rates_device, ctx.rates_dtype = rates.device, rates.dtype
         ctx.ns_is_tensor = torch.is_tensor(ns)
         return J.to(rates.device)
@@ -50,11 +43,10 @@ class FinalStress(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         e = ctx.ensemble
-        g = e.adjoint(ctx.comp, ctx.init_window)                      # [M][10]
-        gk = g[:, :9].reshape(-1, 3, 3)
-        d_rate = (gk * ctx.dirs[ctx.elem]).sum(dim=(1, 2))           # dJ_k/drate_e per chain
-        dr = torch.zeros(e.n_elements, dtype=torch.float64, device=e.device).index_add_(0, ctx.elem, d_rate) / ctx.counts
-        dn = torch.zeros(e.n_elements, dtype=torch.float64, device=e.device).index_add_(0, ctx.elem, g[:, 9]) / ctx.counts
+        g, _ = e.adjoint_elements(ctx.comp, ctx.init_window)         # [E][10] element means
+        # kappa_e = rate_e D_e: dJ_e/drate_e = sum_ab D_e,ab dJ_e/dkappa_e,ab
+        dr = (g[:, :9].reshape(-1, 3, 3) * ctx.dirs).sum(dim=(1, 2))
+        dn = g[:, 9]
         gJ = gJ.to(device=e.device, dtype=torch.float64)
         grad_rates = (gJ * dr).to(device=ctx.rates_device, dtype=ctx.rates_dtype)
         grad_ns = (gJ * dn).sum().to(device=ctx.rates_device) if ctx.ns_is_tensor else None

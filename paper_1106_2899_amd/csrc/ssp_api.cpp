@@ -660,6 +660,24 @@ int ssp_read_stress(ssp_handle* h, double* out_dev, ssp_stream stream)
     return check_flags(h, s);
 }
 
+int ssp_read_element_stress(ssp_handle* h, double* out_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!h->initialized) return fail(h, SSP_ESTATE, "read before ssp_init_equilibrium");
+    if (!out_dev) return fail(h, SSP_EINVAL, "out_dev is required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipSetDevice(h->device));
+    const ssp_config& k = h->res.cfg;
+    // per-chain stress staged in the sample buffer, which holds at least one
+    // sample of every chain and is free between steps (a launch's samples are
+    // consumed by the correlator and series kernels queued right after it)
+    double* per_chain = h->samples();
+    HIPCHK(h, launch_stress(k.precision, h->st(), h->ct(), k.n_chains, k.ns, per_chain, s));
+    HIPCHK(h, launch_element_mean(per_chain, kSampleValues, kSampleValues,
+                                  reinterpret_cast<const int32_t*>(h->work + h->lay.elem_off), k.n_elements, out_dev, s));
+    return check_flags(h, s);
+}
+
 int ssp_read_state(ssp_handle* h, double* R_dev, double* A_dev, int32_t* S_dev, ssp_stream stream)
 {
     if (!h) return SSP_EINVAL;
@@ -734,7 +752,7 @@ int ssp_read_correlator(ssp_handle* h, double* G_dev, double* G_err_dev, double*
     return check_flags(h, s);
 }
 
-int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_dev, ssp_stream stream)
+int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_dev, double* dGv_dev, ssp_stream stream)
 {
     if (!h) return SSP_EINVAL;
     const ssp_config& k = h->res.cfg;
@@ -748,6 +766,15 @@ int ssp_read_correlator_virtual(ssp_handle* h, double* Gv_dev, double* Gv_err_de
                                   k.corr_batches, batch, s));
     HIPCHK(h, launch_corr_final(batch, k.n_chains, k.corr_levels, k.corr_batches, h->corr_samples, Gv_dev, Gv_err_dev,
                                 s));
+    if (dGv_dev) {
+        // G(t) of the same samples into the handle's own output area, then Gv / G
+        double* G = reinterpret_cast<double*>(h->work + h->lay.corr_out);
+        HIPCHK(h, launch_corr_batches(reinterpret_cast<const double*>(h->work + h->lay.acc), k.n_chains, k.corr_levels,
+                                      k.corr_batches, batch, s));
+        HIPCHK(h, launch_corr_final(batch, k.n_chains, k.corr_levels, k.corr_batches, h->corr_samples, G,
+                                    G + (size_t)k.corr_levels * 16, s));
+        HIPCHK(h, launch_grid_ratio(Gv_dev, G, k.corr_levels, h->corr_samples, dGv_dev, s));
+    }
     return check_flags(h, s);
 }
 
@@ -926,8 +953,13 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
     return SSP_OK;
 }
 
-int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
-                double* grad_dev, ssp_stream stream)
+}  // extern "C"
+
+namespace {
+
+// The reverse pass of ssp_adjoint: per-chain gradients into grad_dev [M][10].
+int adjoint_pass(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
+                 double* grad_dev, ssp_stream stream)
 {
     if (!h) return SSP_EINVAL;
     if (!rec_dev || rec_dev != h->rec.ptr) return fail(h, SSP_ESTATE, "rec_dev does not hold the last recorded window");
@@ -1023,6 +1055,29 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
                     "ssp_forward_record, or recorded by another handle); gradients are invalid");
     }
     return check_flags(h, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component, int32_t init_window,
+                double* grad_dev, ssp_stream stream)
+{
+    return adjoint_pass(h, rec_dev, kappa_dev, component, init_window, grad_dev, stream);
+}
+
+int ssp_adjoint_elements(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component,
+                         int32_t init_window, double* chain_grad_dev, double* elem_grad_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!elem_grad_dev || !chain_grad_dev) return fail(h, SSP_EINVAL, "chain_grad_dev and elem_grad_dev are required");
+    const int rc = adjoint_pass(h, rec_dev, kappa_dev, component, init_window, chain_grad_dev, stream);
+    if (rc != SSP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, launch_element_mean(chain_grad_dev, 10, 10, reinterpret_cast<const int32_t*>(h->work + h->lay.elem_off),
+                                  h->res.cfg.n_elements, elem_grad_dev, s));
+    return SSP_OK;
 }
 
 int ssp_set_mapping(ssp_handle* h, int32_t n_lo, int32_t n_hi, int32_t lanes_per_chain, int32_t beads_per_lane)

@@ -499,7 +499,71 @@ __global__ void k_rng_normals(uint32_t k0, uint32_t k1, uint32_t gid, int64_t st
     out[3 * t + 2] = (double)g[o + 2];
 }
 
+// ----------------------------------------------------- element means -------
+// out[e][c] = (1 / M_e) sum over the chains k of element e of rows[k][c],
+// c < ncols: the ensemble average of a per-chain quantity within one fluid
+// element (the average of Sec. 2.1 over the element's chains).  One block per
+// element; thread t takes the chains lo + t, lo + t + 256, ... with Neumaier
+// sums per column, and thread c then adds the 256 partials of column c in
+// thread order, so the result does not depend on timing.
+constexpr int kMeanCols = 12;
+__global__ void __launch_bounds__(kBlock) k_element_mean(const double* rows, int64_t stride, int32_t ncols,
+                                                         const int32_t* elem_off, double* out)
+{
+    const int e = blockIdx.x;
+    const int64_t lo = elem_off[e], hi = elem_off[e + 1];
+    Neumaier nm[kMeanCols];
+    for (int64_t k = lo + threadIdx.x; k < hi; k += kBlock)
+        for (int c = 0; c < kMeanCols; ++c)
+            if (c < ncols) nm[c].add(rows[k * stride + c]);
+    __shared__ double ps[kMeanCols][kBlock], pc[kMeanCols][kBlock];
+    for (int c = 0; c < kMeanCols; ++c) {
+        ps[c][threadIdx.x] = nm[c].s;
+        pc[c][threadIdx.x] = nm[c].c;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ncols) {
+        const int c = threadIdx.x;
+        Neumaier tot;
+        double cc = 0.0;
+        for (int t = 0; t < kBlock; ++t) {
+            tot.add(ps[c][t]);
+            cc += pc[c][t];
+        }
+        out[(int64_t)e * ncols + c] = (tot.value() + cc) / (double)(hi - lo);
+    }
+}
+
+// ratio[t] = num[t] / den[t] on the multiple-tau grid where the lag has data
+// and den != 0, NaN elsewhere (the relative contribution of the virtual
+// stress to G(t), Sec. 4.1).
+__global__ void k_grid_ratio(const double* num, const double* den, int32_t levels, int64_t samples, double* ratio)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= levels * 16) return;
+    const int l = t / 16, k = t % 16;
+    const int64_t len = samples >> l;
+    ratio[t] = (len > k && den[t] != 0.0) ? num[t] / den[t] : __builtin_nan("");
+}
+
 }  // namespace
+
+hipError_t launch_element_mean(const double* rows, int64_t stride, int32_t ncols, const int32_t* elem_off,
+                               int32_t n_elements, double* out, hipStream_t s)
+{
+    if (ncols < 1 || ncols > kMeanCols || n_elements < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_element_mean, dim3((unsigned)n_elements), dim3(kBlock), 0, s, rows, stride, ncols, elem_off,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_ratio(const double* num, const double* den, int32_t levels, int64_t samples, double* ratio,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grid_ratio, dim3(blocks_for(levels * 16)), dim3(kBlock), 0, s, num, den, levels, samples,
+                       ratio);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(int precision, const State& st, const ChainTables& ct, int64_t M, Physics ph, hipStream_t s)
 {

@@ -163,6 +163,10 @@ hipError_t launch_rec_s0(const int32_t* S, int8_t* rec, int64_t total, hipStream
 hipError_t launch_set_ctrl_steps(int64_t* ctrl, int64_t steps, hipStream_t s);
 hipError_t launch_rng_normals(int precision, uint32_t key0, uint32_t key1, uint32_t gid, int64_t step, int32_t bead,
                               int32_t count, double* out, hipStream_t s);
+hipError_t launch_element_mean(const double* rows, int64_t stride, int32_t ncols, const int32_t* elem_off,
+                               int32_t n_elements, double* out, hipStream_t s);
+hipError_t launch_grid_ratio(const double* num, const double* den, int32_t levels, int64_t samples, double* ratio,
+                             hipStream_t s);
 hipError_t launch_moduli(const double* G, int32_t levels, int64_t samples, double sample_dt, const double* omega,
                          int32_t n_omega, double t_lo, double t_hi, double* moduli, double* scalars, hipStream_t s);
 

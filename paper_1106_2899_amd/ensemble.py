@@ -179,6 +179,12 @@ class Ensemble:
         self._chk(lib().ssp_read_stress(self._h, ctypes.c_void_p(out.data_ptr()), self._s))
         return out
 
+    def element_stress(self) -> torch.Tensor:
+        """[E][12] FP64: the mean over each element's chains of sigma then sigma^v."""
+        out = torch.empty((self.n_elements, 12), dtype=torch.float64, device=self.device)
+        self._chk(lib().ssp_read_element_stress(self._h, ctypes.c_void_p(out.data_ptr()), self._s))
+        return out
+
     def step_count(self) -> int:
         """Steps completed since init()."""
         n = ctypes.c_int64()
@@ -230,14 +236,12 @@ class Ensemble:
         L = self.corr_levels
         Gv = torch.empty(L * 16, dtype=torch.float64, device=self.device)
         E = torch.empty(L * 16, dtype=torch.float64, device=self.device)
+        R = torch.empty(L * 16, dtype=torch.float64, device=self.device)
         self._chk(lib().ssp_read_correlator_virtual(self._h, ctypes.c_void_p(Gv.data_ptr()), ctypes.c_void_p(E.data_ptr()),
-                                                    self._s))
+                                                    ctypes.c_void_p(R.data_ptr()), self._s))
         c = self.correlator()
-        gv = Gv.cpu().numpy().reshape(L, 16)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            ratio = np.where(c["G"] != 0.0, gv / c["G"], np.nan)
-        return {"tau": c["tau"], "Gv": gv, "Gv_err": E.cpu().numpy().reshape(L, 16), "counts": c["counts"],
-                "dG_v": ratio}
+        return {"tau": c["tau"], "Gv": Gv.cpu().numpy().reshape(L, 16), "Gv_err": E.cpu().numpy().reshape(L, 16),
+                "counts": c["counts"], "dG_v": R.cpu().numpy().reshape(L, 16)}
 
     def linear_viscoelasticity(self, omega, t_lo: float, t_hi: float, G=None):
         """G'(w), G''(w), |eta*(w)|, eta_0 and tau_d from the relaxation modulus
@@ -291,6 +295,17 @@ class Ensemble:
         self._chk(lib().ssp_adjoint(self._h, ctypes.c_void_p(self._rec_p), ctypes.c_void_p(self._rec_kappa.data_ptr()),
                                     int(component), 1 if init_window else 0, ctypes.c_void_p(out.data_ptr()), self._s))
         return out
+
+    def adjoint_elements(self, component: int = 3, init_window: bool = True):
+        """(elem [E][10], chain [M][10]) FP64: the per-element means (library
+        reduction) and the per-chain values of dJ_k/dkappa (9) and dJ_k/dN_s."""
+        chain = torch.empty((self.M, 10), dtype=torch.float64, device=self.device)
+        elem = torch.empty((self.n_elements, 10), dtype=torch.float64, device=self.device)
+        self._chk(lib().ssp_adjoint_elements(self._h, ctypes.c_void_p(self._rec_p),
+                                             ctypes.c_void_p(self._rec_kappa.data_ptr()), int(component),
+                                             1 if init_window else 0, ctypes.c_void_p(chain.data_ptr()),
+                                             ctypes.c_void_p(elem.data_ptr()), self._s))
+        return elem, chain
 
     def set_mapping(self, n_lo: int, n_hi: int, lanes_per_chain: int, beads_per_lane: int) -> "Ensemble":
         """Chain-to-wavefront mapping for chains with n_lo <= N <= n_hi."""

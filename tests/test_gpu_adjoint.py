@@ -109,6 +109,35 @@ def test_autograd_function_matches_adjoint_means():
     np.testing.assert_allclose(J.detach().cpu().numpy(), o.stress()[:, 3].reshape(E, per).mean(axis=1), rtol=1e-10)
 
 
+def test_element_reductions_of_stress_and_adjoint():
+    """ssp_read_element_stress and ssp_adjoint_elements: per-element means over
+    unequal elements (7, 300 and 13 chains: the middle one spans more chains
+    than the reduction block has threads) against the oracle's per-chain
+    stress and adjoint of the same chains, averaged per element (FP64)."""
+    offs = np.array([0, 7, 307, 320])
+    E, M, N, T = 3, 320, 6, 60
+    rates = np.array([0.3, 0.05, 1.0])
+    kap = np.zeros((E, 3, 3))
+    kap[:, 0, 1] = rates
+    e = _ens(N, M, n_elements=E, element_offsets=offs, precision="fp64", seed=17, corr_levels=0).init()
+    e.forward_record(T, 20, kap.reshape(E, 9))
+    Sel = e.element_stress().cpu().numpy()
+    elem, chain = (x.cpu().numpy() for x in e.adjoint_elements(component=3))
+    kchain = np.repeat(kap.reshape(E, 9), np.diff(offs), axis=0)
+    o = oracle.Ensemble([N] * M, seed=17).init()
+    Rt, At, St = o.run_record(T, kchain)
+    gk, gns = o.adjoint(Rt, At, St, kchain, comp=3)
+    so = o.stress()
+    for q in range(E):
+        sl = slice(offs[q], offs[q + 1])
+        np.testing.assert_allclose(Sel[q], so[sl].mean(axis=0), rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(elem[q, :9], gk[sl].reshape(-1, 9).mean(axis=0), rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(elem[q, 9], gns[sl].mean(), rtol=1e-9, atol=1e-12)
+        # the element means are the means of the per-chain values returned
+        np.testing.assert_allclose(elem[q], chain[sl].mean(axis=0), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(chain[:, 9], gns, rtol=1e-9, atol=1e-12)
+
+
 @pytest.mark.parametrize("change", ["out_of_range", "impossible_move", "first_row", "inner_destruction"])
 @pytest.mark.parametrize("ckpt", [10, 40], ids=["checkpointed", "stored"])
 def test_adjoint_rejects_a_changed_recording_and_keeps_the_ensemble(ckpt, change):

@@ -103,6 +103,7 @@ def test_virtual_stress_channel_matches_oracle_fp64():
     np.testing.assert_allclose(e.correlator()["G"], G, rtol=1e-9, atol=1e-11)
     ok = (cnt > 0) & (np.abs(G) > 1e-3)
     np.testing.assert_allclose(got["dG_v"][ok], Gv[ok] / G[ok], rtol=1e-8)
+    assert np.all(np.isnan(got["dG_v"][cnt == 0]))  # lags without data
     assert np.all(got["Gv_err"][cnt > 0] >= 0)
     plain = _ens(N, M, precision="fp64", seed=6, sample_every=every, corr_levels=L, corr_batches=4).init()
     with pytest.raises(Exception):
