@@ -196,7 +196,7 @@ def batched_configs(md_steps=1000, launches=3):
                      seed=w.seed, sample_every=w.sample_every, corr_levels=0, series_capacity=cap,
                      max_steps_per_launch=md_steps, use_graph=True)
         if tune:
-            autotune.tune(e)
+            autotune.tune(e, w.kappa)
         e.init()
         kap = torch.as_tensor(w.kappa.reshape(w.n_elements, 9), dtype=torch.float64, device="cuda")
         e.step(md_steps, kap)  # graph capture and warm-up

@@ -119,7 +119,9 @@ int ssp_init_equilibrium(ssp_handle* h, ssp_stream stream);
 /* Advances every chain by n_steps >= 0 steps of the three-substep scheme
  * (Sec. 3.1) under the velocity gradient kappa_dev: [E][9] row-major FP64,
  * (kappa.R)_a = sum_b kappa[e][3a+b] R_b, constant over the call (a step
- * strain gamma is ssp_step(h, 1, gamma/dt in xy) followed by kappa = 0).
+ * strain gamma is ssp_step(h, 1, gamma/dt in xy) followed by kappa = 0);
+ * NULL: at rest (kappa = 0 everywhere, by a kernel variant without the flow
+ * terms; the trajectory equals that of a zero table bit for bit).
  * Stress is sampled after every step whose 1-based count is a multiple of
  * sample_every; samples feed the correlator and the element series.
  * Asynchronous.  A non-finite position latches a device flag reported by the
@@ -250,7 +252,7 @@ int ssp_adjoint_bytes(const ssp_handle* h, int64_t window, int32_t ckpt_every, s
  * aligned, ssp_adjoint_bytes long).  With ckpt_every >= window the window is
  * one segment and the forward also stores its positions and the anchors the
  * reverse pass needs, so that ssp_adjoint replays nothing (memory for time).
- * kappa_dev as in ssp_step.  Asynchronous. */
+ * kappa_dev as in ssp_step (NULL: at rest).  Asynchronous. */
 int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const double* kappa_dev, void* rec_dev,
                        ssp_stream stream);
 
@@ -261,7 +263,7 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
  * FP64 receives dJ_k/dkappa_ab (row-major, 9 values) and dJ_k/dN_s for
  * J_k = sigma_component of chain k at the end of the window (component 0..5
  * = xx yy zz xy yz zx).  kappa_dev must hold the velocity gradient of the
- * recorded window.  init_window != 0 adds the N_s dependence of the sampled
+ * recorded window (NULL: at rest).  init_window != 0 adds the N_s dependence of the sampled
  * initial anchors when the window started at step 0.  Synchronises.  Every
  * recorded slot row is checked as it is read (a state the step could have
  * produced from the one before); a recording changed since
@@ -283,6 +285,19 @@ int ssp_adjoint(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int
  * elem_grad_dev is not written. */
 int ssp_adjoint_elements(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component,
                          int32_t init_window, double* chain_grad_dev, double* elem_grad_dev, ssp_stream stream);
+
+/* ssp_adjoint_elements for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same element means into elem_grad_dev [E][10] FP64, with
+ * the per-chain gradients kept in a static device array of the library
+ * instead of a caller workspace.  Allocates nothing and calls no allocating
+ * routine.  At most 262144 chains (SSP_ESIZE beyond).  The array (20 MiB per
+ * GPU, held until the process ends) is shared by every handle on a GPU, so
+ * calls that overlap on one GPU race; it keeps the last call's contents, and
+ * each call clears what it uses.  Other arguments, synchronisation and errors
+ * as ssp_adjoint_elements. */
+int ssp_adjoint_elements_noalloc(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component,
+                                 int32_t init_window, double* elem_grad_dev, ssp_stream stream);
 
 /* Chain-to-wavefront mapping for the chains with n_lo <= N <= n_hi: each
  * such chain occupies lanes_per_chain lanes (8, 16, 32 or 64) with

@@ -42,6 +42,7 @@ EXPORTS = [
     "ssp_forward_record",
     "ssp_adjoint",
     "ssp_adjoint_elements",
+    "ssp_adjoint_elements_noalloc",
     "ssp_set_mapping",
     "ssp_set_kernel_timing",
     "ssp_kernel_time",
@@ -119,6 +120,7 @@ def lib():
             "ssp_forward_record": [vp, i64, i32, vp, vp, vp],
             "ssp_adjoint": [vp, vp, vp, i32, i32, vp, vp],
             "ssp_adjoint_elements": [vp, vp, vp, i32, i32, vp, vp, vp],
+            "ssp_adjoint_elements_noalloc": [vp, vp, vp, i32, i32, vp, vp],
             "ssp_set_mapping": [vp, i32, i32, i32, i32],
             "ssp_set_kernel_timing": [vp, ctypes.c_int],
             "ssp_kernel_time": [vp, f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],

@@ -16,6 +16,9 @@
 //   dJ/dA_m     = (1 + dt kappa^T) lA (surviving) + dt (3/N_s) lR[S_m],
 //   dJ/dR_m     = lR + dt (L lR - (3/N_s) c lR + kappa^T lR),
 // L the free-end bond Laplacian (stiffness 3) and c the springs per bead.
+#include <mutex>
+#include <vector>
+
 #include "ssp_device.h"
 #include "ssp_internal.h"
 
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     T kap[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        kap[q] = valid ? T(a.kappa[9 * elem + q]) : T(0);
+        kap[q] = (valid && a.kappa) ? T(a.kappa[9 * elem + q]) : T(0);  // no table: at rest
         // one chain per wavefront: its element's kappa is wave-uniform
         if constexpr (W == kWaveSize) kap[q] = wave_uniform(kap[q]);
     }
@@ -128,7 +131,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         double K[9], M[9], Mi[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            K[q] = valid ? (double)T(a.ph.dt * a.kappa[9 * elem + q]) : 0.0;
+            K[q] = (valid && a.kappa) ? (double)T(a.ph.dt * a.kappa[9 * elem + q]) : 0.0;
             M[q] = K[q] + ((q % 4 == 0) ? 1.0 : 0.0);
         }
         Mi[0] = M[4] * M[8] - M[5] * M[7];
@@ -514,6 +517,38 @@ __global__ void k_set_ctrl_steps(int64_t* ctrl, int64_t steps)
 }
 
 }  // namespace
+
+// Scratch of the allocation-free reverse pass (ssp_adjoint_elements_noalloc):
+// the per-chain gradients [kNoAllocMaxChains][10] FP64 that the element means
+// are reduced from.  Every GPU the library runs on holds one copy (20 MiB)
+// until the process ends; all calls on a GPU share it.  Host code never passes
+// the array's name to a kernel: it is a host-side stand-in, and the device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[kNoAllocMaxChains * 10];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // per device, null until looked up
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double** ptr)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((size_t)device >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the device must be current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_adjoint(int precision, int W, int B, const AdjointArgs& a, hipStream_t s)
 {

@@ -275,6 +275,10 @@ struct ssp_handle {
     std::map<std::pair<int64_t, const double*>, hipGraphExec_t> graphs;
     std::string err;
     std::string warning;  // set at creation (cap_warning)
+    // device address of the static scratch of the allocation-free reverse
+    // pass, looked up at creation (null if the lookup failed; hipError kept)
+    double* noalloc = nullptr;
+    hipError_t noalloc_err = hipSuccess;
     // kernel timing mode: events bracket every step-kernel launch
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -551,6 +555,7 @@ int ssp_create(const ssp_config* cfg, void* state_dev, void* work_dev, ssp_handl
         delete h;
         return SSP_EHIP;
     }
+    h->noalloc_err = noalloc_scratch(h->device, &h->noalloc);
     const int64_t M = h->res.cfg.n_chains;
     // host tables
     std::vector<int64_t> off(M);
@@ -617,7 +622,6 @@ int ssp_step(ssp_handle* h, int64_t n_steps, const double* kappa_dev, ssp_stream
     if (!h) return SSP_EINVAL;
     if (!h->initialized) return fail(h, SSP_ESTATE, "ssp_step before ssp_init_equilibrium");
     if (n_steps < 0) return fail(h, SSP_EINVAL, "n_steps must be >= 0");
-    if (!kappa_dev) return fail(h, SSP_EINVAL, "kappa_dev is required");
     if (n_steps == 0) return SSP_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIPCHK(h, hipSetDevice(h->device));
@@ -907,8 +911,8 @@ int ssp_forward_record(ssp_handle* h, int64_t window, int32_t ckpt_every, const 
 {
     if (!h) return SSP_EINVAL;
     if (!h->initialized) return fail(h, SSP_ESTATE, "ssp_forward_record before ssp_init_equilibrium");
-    if (window < 1 || ckpt_every < 1 || !kappa_dev || !rec_dev)
-        return fail(h, SSP_EINVAL, "window >= 1, ckpt_every >= 1, kappa_dev and rec_dev are required");
+    if (window < 1 || ckpt_every < 1 || !rec_dev)
+        return fail(h, SSP_EINVAL, "window >= 1, ckpt_every >= 1 and rec_dev are required");
     if (reinterpret_cast<uintptr_t>(rec_dev) % kAlign) return fail(h, SSP_EINVAL, "rec_dev must be 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIPCHK(h, hipSetDevice(h->device));
@@ -963,8 +967,8 @@ int adjoint_pass(ssp_handle* h, const void* rec_dev, const double* kappa_dev, in
 {
     if (!h) return SSP_EINVAL;
     if (!rec_dev || rec_dev != h->rec.ptr) return fail(h, SSP_ESTATE, "rec_dev does not hold the last recorded window");
-    if (!kappa_dev || !grad_dev || component < 0 || component > 5)
-        return fail(h, SSP_EINVAL, "kappa_dev, grad_dev and component 0..5 are required");
+    if (!grad_dev || component < 0 || component > 5)
+        return fail(h, SSP_EINVAL, "grad_dev and component 0..5 are required");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIPCHK(h, hipSetDevice(h->device));
     const ssp_config& k = h->res.cfg;
@@ -1076,6 +1080,25 @@ int ssp_adjoint_elements(ssp_handle* h, const void* rec_dev, const double* kappa
     if (rc != SSP_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIPCHK(h, launch_element_mean(chain_grad_dev, 10, 10, reinterpret_cast<const int32_t*>(h->work + h->lay.elem_off),
+                                  h->res.cfg.n_elements, elem_grad_dev, s));
+    return SSP_OK;
+}
+
+int ssp_adjoint_elements_noalloc(ssp_handle* h, const void* rec_dev, const double* kappa_dev, int32_t component,
+                                 int32_t init_window, double* elem_grad_dev, ssp_stream stream)
+{
+    if (!h) return SSP_EINVAL;
+    if (!elem_grad_dev) return fail(h, SSP_EINVAL, "elem_grad_dev is required");
+    if (h->res.cfg.n_chains > kNoAllocMaxChains)
+        return fail(h, SSP_ESIZE, "ssp_adjoint_elements_noalloc handles at most 262144 chains (its static scratch); "
+                                  "use ssp_adjoint_elements with a workspace");
+    if (!h->noalloc)
+        return fail(h, SSP_EHIP, std::string("the static scratch of this device is not available: ") +
+                                     hipGetErrorString(h->noalloc_err));
+    const int rc = adjoint_pass(h, rec_dev, kappa_dev, component, init_window, h->noalloc, stream);
+    if (rc != SSP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, launch_element_mean(h->noalloc, 10, 10, reinterpret_cast<const int32_t*>(h->work + h->lay.elem_off),
                                   h->res.cfg.n_elements, elem_grad_dev, s));
     return SSP_OK;
 }

@@ -209,4 +209,97 @@ __device__ __forceinline__ void cadd3(v3<float>& hi, v3<float>& lo, v3<float> in
     cadd(hi.z, lo.z, inc.z);
 }
 
+// Error-free transformations (Knuth's TwoSum; the FMA form of the exact
+// product): s + t = a + b and p + e = a b exactly in binary32.  Contraction is
+// off so that the compiler cannot fuse a product into a later sum.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& t)
+{
+#pragma clang fp contract(off)
+    s = a + b;
+    const float bb = s - a;
+    t = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e)
+{
+#pragma clang fp contract(off)
+    p = a * b;
+    e = __builtin_fmaf(a, b, -p);
+}
+
+// Row r of the affine flow increment K (h + l) of a compensated position
+// (h, l), K = dt kappa, as big + small: big is the binary32 sum of the
+// products K_rc h_c, small carries the rounding errors of those products and
+// sums and the products with the low part, K_rc l_c.  `mask` marks the
+// entries of K that are nonzero anywhere in the wavefront (a wave-uniform
+// value: the tests are uniform branches).
+template <int R>
+__device__ __forceinline__ void flow_row(const float* K, uint32_t mask, v3<float> h, v3<float> l, float& big,
+                                         float& small)
+{
+#pragma clang fp contract(off)
+    const float hc[3] = {h.x, h.y, h.z};
+    const float lc[3] = {l.x, l.y, l.z};
+    big = 0.0f;
+    small = 0.0f;
+    bool first = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (mask & (1u << (3 * R + c))) {
+            float p, e;
+            two_prod(K[3 * R + c], hc[c], p, e);
+            small = small + __builtin_fmaf(K[3 * R + c], lc[c], e);
+            if (first) {
+                big = p;
+                first = false;
+            } else {
+                float s, t;
+                two_sum(big, p, s, t);
+                big = s;
+                small = small + t;
+            }
+        }
+    }
+}
+
+// K v for the entries of K marked in `mask` (wave-uniform; the others are
+// known to be zero in every lane), as fused multiply-adds in row order.
+__device__ __forceinline__ v3<float> masked_mat3(const float* K, uint32_t mask, v3<float> v)
+{
+    const float vc[3] = {v.x, v.y, v.z};
+    float r[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (mask & (1u << (3 * a + c))) r[a] = __builtin_fmaf(K[3 * a + c], vc[c], r[a]);
+    return {r[0], r[1], r[2]};
+}
+
+// (h, l) += big + inc, with big added error-free: the rounding of h + big is
+// carried into l before the renormalisation.
+__device__ __forceinline__ void cadd_big(float& hi, float& lo, float big, float inc)
+{
+#pragma clang fp contract(off)
+    float s, t;
+    two_sum(hi, big, s, t);
+    const float y = (inc + t) + lo;
+    hi = s + y;
+    lo = y - (hi - s);
+}
+
+// One component of the error-free move of a stretched chain:
+// (h, l) += (big + small) + c lap + rest, where big + small is the flow term
+// (flow_row), c lap the bond force (lap from the compensated positions) and
+// rest the noise and slip-spring force.  The bond force is split exactly
+// (two_prod) and its large part joined to big by an exact TwoSum.
+__device__ __forceinline__ void cadd_force(float& hi, float& lo, float big, float small, float c, float lap,
+                                           float rest)
+{
+#pragma clang fp contract(off)
+    float pf, ef, tot, t;
+    two_prod(c, lap, pf, ef);
+    two_sum(big, pf, tot, t);
+    cadd_big(hi, lo, tot, rest + ((small + ef) + t));
+}
+
 }  // namespace ssp

@@ -14,6 +14,9 @@ constexpr int kMaxBeads = 128;
 constexpr int kSampleValues = 12;  // sigma (6) then sigma^v (6)
 constexpr int kCorrLags = 16;
 constexpr int kMaxCorrLevels = 16;
+// Chains the allocation-free reverse pass can reduce (its static scratch holds
+// 10 FP64 gradients per chain: 20 MiB per GPU).
+constexpr int64_t kNoAllocMaxChains = int64_t(1) << 18;
 
 // ctrl[] words in the work buffer (device-resident so that captured graphs
 // can be replayed at any step count).
@@ -163,6 +166,9 @@ hipError_t launch_rec_s0(const int32_t* S, int8_t* rec, int64_t total, hipStream
 hipError_t launch_set_ctrl_steps(int64_t* ctrl, int64_t steps, hipStream_t s);
 hipError_t launch_rng_normals(int precision, uint32_t key0, uint32_t key1, uint32_t gid, int64_t step, int32_t bead,
                               int32_t count, double* out, hipStream_t s);
+// Device address of the static scratch of ssp_adjoint_elements_noalloc on
+// `device`, which must be current (looked up once per device).
+hipError_t noalloc_scratch(int device, double** ptr);
 hipError_t launch_element_mean(const double* rows, int64_t stride, int32_t ncols, const int32_t* elem_off,
                                int32_t n_elements, double* out, hipStream_t s);
 hipError_t launch_grid_ratio(const double* num, const double* den, int32_t levels, int64_t samples, double* ratio,

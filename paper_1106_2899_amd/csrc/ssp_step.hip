@@ -142,7 +142,11 @@ template <typename T, int B, bool SAMP> struct WaveLds {
 // (positions every step, the anchors the adjoint cannot rebuild), so that the
 // reverse pass of a one-segment window needs no replay.  Its destroyed-spring
 // anchors go to a compact per-chain log instead of a dense plane.
-template <typename T, int W, int B, bool K1, bool RP, bool ST>
+// FL: compiled with the flow terms (a velocity gradient table is given); a
+// run at rest (no table) uses the variant without them, whose registers are
+// not shared with the flow code.  The two give identical trajectories at
+// kappa = 0.
+template <typename T, int W, int B, bool K1, bool RP, bool ST, bool FL>
 __device__ __forceinline__ void step_body(const StepArgs& a)
 {
     constexpr bool kComp = std::is_same<T, float>::value;  // (hi, lo) position sums
@@ -184,16 +188,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     const uint32_t k0 = a.ph.key0, k1 = a.ph.key1;
 
     T kdt[9];  // dt kappa of the chain's element
-    bool has_flow = false;
+    uint32_t kmask = 0;  // entries of kappa that are nonzero in some chain of the wavefront
+    bool chain_flow = false;  // this lane's chain has a nonzero kappa
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const double kq = valid ? a.kappa[9 * elem + q] : 0.0;
-        kdt[q] = T(a.ph.dt * kq);
-        // one chain per wavefront: its element's kappa is wave-uniform
-        if constexpr (W == kWaveSize) kdt[q] = wave_uniform(kdt[q]);
-        has_flow |= kq != 0.0;
+        kdt[q] = T(0);
+        if constexpr (FL) {
+            const double kq = valid ? a.kappa[9 * elem + q] : 0.0;
+            kdt[q] = T(a.ph.dt * kq);
+            // one chain per wavefront: its element's kappa is wave-uniform
+            if constexpr (W == kWaveSize) kdt[q] = wave_uniform(kdt[q]);
+            if (wave_any(kq != 0.0)) kmask |= 1u << q;
+            chain_flow |= kq != 0.0;
+        }
     }
-    const bool flow = wave_any(has_flow);
+    const bool flow = FL && kmask != 0;
+    // elongation (a positive diagonal entry of kappa) stretches chains without
+    // bound above the Rouse instability: such chains take the error-free move
+    const bool chain_stretch = chain_flow && (kdt[0] > T(0) || kdt[4] > T(0) || kdt[8] > T(0));
 
     v3<T> rh[B], rl[B], ah[B], al[B], d[B], br[B], bl[B];
     int s[B];
@@ -456,32 +468,101 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         if (any_pend) atomicOr(a.flags, kFlagInternal);
 
         // ---- substep 1b: Euler-Maruyama for beads, advection for anchors.
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int i = li * B + b;
+        // FP32 under flow: positions drift and stretch far from the origin
+        // while bonds near the chain ends and anchor offsets stay O(1), so the
+        // terms of the move that scale with |R| must keep their low bits:
+        //  - beads: the flow term takes dt kappa (hi + lo); the low part's
+        //    product is small but systematic and would add up over the steps;
+        //  - anchors: advected error-free (flow_row, cadd_big); under shear an
+        //    anchor's increment dt gamma_dot A_y is the same number every
+        //    step, so its rounding error would add up linearly;
+        //  - chains under elongation (a positive diagonal entry of kappa),
+        //    which stretch to bonds of hundreds: the bead's flow term and its
+        //    bond force, taken from the compensated positions, split into a
+        //    binary32 value and its exact rounding error (flow_row,
+        //    two_prod); the large part enters hi through an exact TwoSum
+        //    (cadd_big), so that only O(1) quantities are ever rounded.
+        // Which form a chain takes depends only on its own element, and chains
+        // without flow keep the plain binary32 step, so trajectories do not
+        // depend on the mapping or the launch split.
+        auto plain_inc = [&](int b) {
             v3<T> inc = noise[b];
             inc = fma3(cbond, br[b] - bl[b], inc);
-            inc = fma3(-cspring, acc[b], inc);
-            // wave-uniform branch; fma(0, r, x) = x keeps chains without flow bit-identical
-            if (flow) inc = fma_mat3(kdt, rh[b], inc);
-            if (i < n) {
-                if constexpr (kComp)
-                    cadd3(rh[b], rl[b], inc);
-                else
-                    rh[b] = rh[b] + inc;
+            return fma3(-cspring, acc[b], inc);
+        };
+        if constexpr (kComp) {
+            if (flow) {  // wave-uniform
+                if (wave_any(chain_stretch)) {
+                    const v3<T> nh = from_next3(rh[0]), nl = from_next3(rl[0]);
+                    const v3<T> ph = from_prev3(rh[B - 1]), pl = from_prev3(rl[B - 1]);
+                    v3<T> lap[B];  // every bead reads its in-lane neighbours before any moves
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        const int i = li * B + b;
+                        const v3<T> h1 = (b + 1 < B) ? rh[b + 1 < B ? b + 1 : b] : nh;
+                        const v3<T> l1 = (b + 1 < B) ? rl[b + 1 < B ? b + 1 : b] : nl;
+                        const v3<T> h0 = (b > 0) ? rh[b > 0 ? b - 1 : 0] : ph;
+                        const v3<T> l0 = (b > 0) ? rl[b > 0 ? b - 1 : 0] : pl;
+                        const bool right = i < n - 1, left = i > 0;
+                        // (R_{i+1} - R_i) - (R_i - R_{i-1}) from the compensated parts
+                        lap[b] = (sel(right, h1 - rh[b], zero3<T>()) - sel(left, rh[b] - h0, zero3<T>())) +
+                                 (sel(right, l1 - rl[b], zero3<T>()) - sel(left, rl[b] - l0, zero3<T>()));
+                    }
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        if (li * B + b < n && chain_stretch) {
+                            const v3<T> rest = fma3(-cspring, acc[b], noise[b]);
+                            v3<T> big, small;
+                            flow_row<0>(kdt, kmask, rh[b], rl[b], big.x, small.x);
+                            flow_row<1>(kdt, kmask, rh[b], rl[b], big.y, small.y);
+                            flow_row<2>(kdt, kmask, rh[b], rl[b], big.z, small.z);
+                            cadd_force(rh[b].x, rl[b].x, big.x, small.x, cbond, lap[b].x, rest.x);
+                            cadd_force(rh[b].y, rl[b].y, big.y, small.y, cbond, lap[b].y, rest.y);
+                            cadd_force(rh[b].z, rl[b].z, big.z, small.z, cbond, lap[b].z, rest.z);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    if (li * B + b < n && !chain_stretch) {
+                        v3<T> inc = plain_inc(b);
+                        if (chain_flow) inc = inc + (masked_mat3(kdt, kmask, rh[b]) + masked_mat3(kdt, kmask, rl[b]));
+                        cadd3(rh[b], rl[b], inc);
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    if (s[b] >= 0 && chain_flow) {
+                        v3<T> big, small;
+                        flow_row<0>(kdt, kmask, ah[b], al[b], big.x, small.x);
+                        flow_row<1>(kdt, kmask, ah[b], al[b], big.y, small.y);
+                        flow_row<2>(kdt, kmask, ah[b], al[b], big.z, small.z);
+                        if (kmask & 0x007u) cadd_big(ah[b].x, al[b].x, big.x, small.x);
+                        if (kmask & 0x038u) cadd_big(ah[b].y, al[b].y, big.y, small.y);
+                        if (kmask & 0x1C0u) cadd_big(ah[b].z, al[b].z, big.z, small.z);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    if (li * B + b < n) cadd3(rh[b], rl[b], plain_inc(b));
             }
-        }
-        if (flow) {
+        } else {
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const v3<T> A = ah[b];
-                const v3<T> inc = {kdt[0] * A.x + kdt[1] * A.y + kdt[2] * A.z, kdt[3] * A.x + kdt[4] * A.y + kdt[5] * A.z,
-                                   kdt[6] * A.x + kdt[7] * A.y + kdt[8] * A.z};
-                if (s[b] >= 0) {
-                    if constexpr (kComp)
-                        cadd3(ah[b], al[b], inc);
-                    else
-                        ah[b] = ah[b] + inc;
+                v3<T> inc = plain_inc(b);
+                // wave-uniform branch; fma(0, r, x) = x keeps chains without flow bit-identical
+                if (flow) inc = fma_mat3(kdt, rh[b], inc);
+                if (li * B + b < n) rh[b] = rh[b] + inc;
+            }
+            if (flow) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const v3<T> A = ah[b];
+                    const v3<T> inc = {kdt[0] * A.x + kdt[1] * A.y + kdt[2] * A.z,
+                                       kdt[3] * A.x + kdt[4] * A.y + kdt[5] * A.z,
+                                       kdt[6] * A.x + kdt[7] * A.y + kdt[8] * A.z};
+                    if (s[b] >= 0) ah[b] = ah[b] + inc;
                 }
             }
         }
@@ -756,40 +837,48 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
 template <typename T, int B>
 constexpr int kStepWavesPerEu = std::is_same<T, float>::value ? (B == 1 ? 5 : 4) : (B == 1 ? 3 : 1);
 
-template <typename T, int W, int B, bool K1, bool ST>
+template <typename T, int W, int B, bool K1, bool ST, bool FL>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>)))
 k_step(StepArgs a)
 {
-    step_body<T, W, B, K1, false, ST>(a);
+    step_body<T, W, B, K1, false, ST, FL>(a);
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
 // segment's trajectory this way).  It samples no stress: without the sampling
 // code and its LDS partials, FP32 with one bead per lane fits 6 waves per SIMD
 // (79 VGPRs, 17 KB of LDS per group) with no spills.
-template <typename T, int W, int B>
+template <typename T, int W, int B, bool FL>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && B == 1 ? 6 : 1)))
 k_replay(StepArgs a)
 {
-    step_body<T, W, B, false, true, false>(a);
+    step_body<T, W, B, false, true, false, FL>(a);
 }
 
+template <typename T, int W, int B, bool FL> hipError_t launch_f(const StepArgs& a, dim3 grid, hipStream_t s)
+{
+    if (a.replay_s)
+        hipLaunchKernelGGL((k_replay<T, W, B, FL>), grid, dim3(kGroupThreads), 0, s, a);
+    else if (a.traj && a.construct_rule == 1)
+        hipLaunchKernelGGL((k_step<T, W, B, true, true, FL>), grid, dim3(kGroupThreads), 0, s, a);
+    else if (a.traj)
+        hipLaunchKernelGGL((k_step<T, W, B, false, true, FL>), grid, dim3(kGroupThreads), 0, s, a);
+    else if (a.construct_rule == 1)
+        hipLaunchKernelGGL((k_step<T, W, B, true, false, FL>), grid, dim3(kGroupThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step<T, W, B, false, false, FL>), grid, dim3(kGroupThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// A null velocity-gradient table means a run at rest: the variant without the
+// flow terms.
 template <typename T, int W, int B> hipError_t launch_t(const StepArgs& a, hipStream_t s)
 {
     constexpr int kChainsPerGroup = kWavesPerGroup * (kWaveSize / W);
     const int64_t groups = (a.n_tasks + kChainsPerGroup - 1) / kChainsPerGroup;
     if (groups == 0) return hipSuccess;
-    if (a.replay_s)
-        hipLaunchKernelGGL((k_replay<T, W, B>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
-    else if (a.traj && a.construct_rule == 1)
-        hipLaunchKernelGGL((k_step<T, W, B, true, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
-    else if (a.traj)
-        hipLaunchKernelGGL((k_step<T, W, B, false, true>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
-    else if (a.construct_rule == 1)
-        hipLaunchKernelGGL((k_step<T, W, B, true, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step<T, W, B, false, false>), dim3((unsigned)groups), dim3(kGroupThreads), 0, s, a);
-    return hipGetLastError();
+    const dim3 grid((unsigned)groups);
+    return a.kappa ? launch_f<T, W, B, true>(a, grid, s) : launch_f<T, W, B, false>(a, grid, s);
 }
 
 template <typename T> hipError_t launch_p(int W, int B, const StepArgs& a, hipStream_t s)

@@ -160,11 +160,19 @@ class Ensemble:
         k = k.reshape(self.n_elements, 9).contiguous()
         return k
 
-    def step(self, n_steps: int, kappa=None) -> "Ensemble":
-        """Advance n_steps steps under velocity gradient kappa (per element)."""
+    def _kappa_arg(self, kappa):
+        """(device table or None, pointer): None is a run at rest (the library's
+        variant without flow terms; the same trajectory as a zero table)."""
+        if kappa is None:
+            return None, ctypes.c_void_p(None)
         k = self.kappa_tensor(kappa)
+        return k, ctypes.c_void_p(k.data_ptr())
+
+    def step(self, n_steps: int, kappa=None) -> "Ensemble":
+        """Advance n_steps steps under velocity gradient kappa (per element; None: at rest)."""
+        k, kp = self._kappa_arg(kappa)
         self._last_kappa = k  # keep alive while the stream may still read it
-        self._chk(lib().ssp_step(self._h, int(n_steps), ctypes.c_void_p(k.data_ptr()), self._s))
+        self._chk(lib().ssp_step(self._h, int(n_steps), kp, self._s))
         return self
 
     @property
@@ -282,9 +290,9 @@ class Ensemble:
             with torch.cuda.device(self.device):
                 self._rec_t, self._rec_p = _aligned_buffer(nbytes.value, self.device)
             self._rec_bytes = nbytes.value
-        k = self.kappa_tensor(kappa)
-        self._rec_kappa = k
-        self._chk(lib().ssp_forward_record(self._h, int(window), int(ckpt_every), ctypes.c_void_p(k.data_ptr()),
+        k, kp = self._kappa_arg(kappa)
+        self._rec_kappa, self._rec_kappa_p = k, kp
+        self._chk(lib().ssp_forward_record(self._h, int(window), int(ckpt_every), kp,
                                            ctypes.c_void_p(self._rec_p), self._s))
         return self
 
@@ -292,7 +300,7 @@ class Ensemble:
         """[M][10] FP64: dJ_k/dkappa (9, row-major) and dJ_k/dN_s for J_k = the
         final stress component of chain k over the last recorded window."""
         out = torch.empty((self.M, 10), dtype=torch.float64, device=self.device)
-        self._chk(lib().ssp_adjoint(self._h, ctypes.c_void_p(self._rec_p), ctypes.c_void_p(self._rec_kappa.data_ptr()),
+        self._chk(lib().ssp_adjoint(self._h, ctypes.c_void_p(self._rec_p), self._rec_kappa_p,
                                     int(component), 1 if init_window else 0, ctypes.c_void_p(out.data_ptr()), self._s))
         return out
 
@@ -301,8 +309,7 @@ class Ensemble:
         reduction) and the per-chain values of dJ_k/dkappa (9) and dJ_k/dN_s."""
         chain = torch.empty((self.M, 10), dtype=torch.float64, device=self.device)
         elem = torch.empty((self.n_elements, 10), dtype=torch.float64, device=self.device)
-        self._chk(lib().ssp_adjoint_elements(self._h, ctypes.c_void_p(self._rec_p),
-                                             ctypes.c_void_p(self._rec_kappa.data_ptr()), int(component),
+        self._chk(lib().ssp_adjoint_elements(self._h, ctypes.c_void_p(self._rec_p), self._rec_kappa_p, int(component),
                                              1 if init_window else 0, ctypes.c_void_p(chain.data_ptr()),
                                              ctypes.c_void_p(elem.data_ptr()), self._s))
         return elem, chain

@@ -13,6 +13,20 @@ counted and the oracle adopts the GPU's decision for that step (teacher
 forcing: the step is re-run from the saved state with the GPU's slot row, by
 the oracle's frozen-event step), so that every chain stays compared to the
 end.  On the FP64 path no tie is tolerated.
+
+Bonds and anchor offsets next to strongly stretched bonds (elongation beyond
+the Rouse instability stretches bonds to hundreds of times their rest length)
+carry an extra, derived allowance on the FP32 path.  A bead there sits where
+bond tensions of size k_b |b| balance, so any relative perturbation eps of
+those forces moves it by eps k_b |b| / k, k the stiffness that restores the
+compared quantity: k_b for a bond (k_b / k = 1), the slip spring's
+k_s = 3/N_s for an anchor offset (k_b / k = N_s).  binary32 arithmetic
+perturbs the forces by a few units of 2^-24 per step (the rounded normals,
+bond vectors, stiffness constants and sums), so the allowance is
+8 * 2^-24 * (k_b / k) * |b|, |b| the longest bond at the compared bond's or
+spring's beads (oracle): below 1e-7 near rest length, about 2e-4 at
+|b| = 500.  (On the CPU the oracle's own FP64 step with only its normals
+rounded to binary32 moves such an anchor offset by about 5e-9 |b|.)
 """
 from __future__ import annotations
 
@@ -20,6 +34,7 @@ import numpy as np
 
 SCALE = 0.58
 TIE = 1e-5
+STRETCH = 8.0 * 2.0 ** -24  # binary32 force perturbation per step, in units of the bond tension
 
 
 class Layout:
@@ -36,6 +51,32 @@ class Layout:
         self.has_bond = np.ones(self.total, dtype=bool)
         self.has_bond[last] = False
         self.bond_idx = np.nonzero(self.has_bond)[0]
+
+    def bond_lengths(self, R):
+        """Per bond (bead i -> i+1): the longest of it and its neighbouring bonds."""
+        b = np.linalg.norm(R[self.bond_idx + 1] - R[self.bond_idx], axis=1)
+        per_bead = np.zeros(self.total)
+        per_bead[self.bond_idx] = b
+        left = np.zeros(self.total)
+        left[self.bond_idx + 1] = b
+        right_next = np.zeros(self.total)
+        right_next[:-1] = per_bead[1:]
+        # neighbours of bond i: bond i-1 (left of bead i) and bond i+1 (right of bead i+1);
+        # a chain's first/last bond has zeros there (no bond crosses chains)
+        nxt = np.where(self.has_bond[self.bond_idx + 1], right_next[self.bond_idx], 0.0)
+        return np.maximum(np.maximum(b, left[self.bond_idx]), nxt)
+
+    def adjacent_bond(self, R, S):
+        """Per slot: the length of the longer bond at the slot's bead (0 if empty)."""
+        b = np.linalg.norm(R[self.bond_idx + 1] - R[self.bond_idx], axis=1)
+        bl = np.zeros(self.total)
+        bl[self.bond_idx] = b              # bond to the right of a bead
+        br = np.zeros(self.total)
+        br[self.bond_idx + 1] = b          # bond to the left of a bead
+        both = np.maximum(bl, br)
+        occ = S >= 0
+        bead = self.off[self.chain] + np.where(occ, S, 0)
+        return np.where(occ, both[bead], 0.0)
 
     def invariants(self, R, A, S):
         """bonds [n_bonds][3] (bead i -> i+1 of each chain), anchor offsets
@@ -115,8 +156,16 @@ def lockstep(e, o, steps, kappa_elem=None, kappa_chain=None, tol=1e-5, fp64=Fals
             assert np.array_equal(S, o.S)
         bg, dg, _ = lay.invariants(R, A, S)
         bo, do, occ = lay.invariants(o.R, o.A, o.S)
-        eb = rel_err(bg, bo).max() if len(bg) else 0.0
-        ed = rel_err(dg[occ], do[occ]).max() if occ.any() else 0.0
+        eb = 0.0
+        if len(bg):
+            allow_b = 0.0 if fp64 else STRETCH * lay.bond_lengths(o.R)[:, None]
+            eb = (np.abs(bg - bo) / (np.maximum(np.abs(bo), SCALE) + allow_b / tol)).max()
+        ed = 0.0
+        if occ.any():
+            # the offset bar in units of tol: tol max(|d|, 0.58) plus the
+            # stretched-bond allowance (FP32 only; see the module docstring)
+            allow = 0.0 if fp64 else STRETCH * o.ns * lay.adjacent_bond(o.R, o.S)[occ][:, None]
+            ed = (np.abs(dg[occ] - do[occ]) / (np.maximum(np.abs(do[occ]), SCALE) + allow / tol)).max()
         worst = max(worst, eb, ed)
         if not (eb <= tol and ed <= tol):
             raise AssertionError(f"step {t}: bond error {eb:.3e}, anchor-offset error {ed:.3e} (bar {tol}); "

@@ -64,6 +64,45 @@ def test_chunking_and_graph_invariance_bitwise():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_run_at_rest_equals_a_zero_velocity_gradient_table_bitwise(precision):
+    """ssp_step with no table (the variant compiled without the flow terms)
+    and with an all-zero table (the flow variant, whose flow branch is then
+    skipped) give the same trajectory and correlator bit for bit."""
+    kw = dict(precision=precision, seed=19, sample_every=2, corr_levels=6, corr_batches=4)
+    a = _ens(24, 40, **kw).init()
+    b = _ens(24, 40, **kw).init()
+    a.step(400)
+    b.step(400, np.zeros(9))
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)
+    assert np.array_equal(a.correlator()["G"], b.correlator()["G"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_flowing_and_resting_chains_in_one_wavefront(precision):
+    """Chains at rest that share wavefronts with sheared chains (8 lanes per
+    chain: eight chains per wavefront, elements of three chains) follow the
+    same trajectory as in an ensemble at rest."""
+    N, M = 8, 48
+    offs = np.arange(0, M + 1, 3)
+    E = len(offs) - 1
+    kap = np.zeros((E, 9))
+    kap[::2, 1] = 0.7  # every other element sheared
+    kw = dict(precision=precision, seed=23, corr_levels=0)
+    a = _ens(N, M, n_elements=E, element_offsets=offs, **kw).init()
+    b = _ens(N, M, **kw).init()
+    a.step(300, kap)
+    b.step(300)
+    Ra, Aa, Sa = (x.cpu().numpy() for x in a.state())
+    Rb, Ab, Sb = (x.cpu().numpy() for x in b.state())
+    rest = np.repeat(np.arange(E) % 2 == 1, 3 * N)
+    assert np.array_equal(Sa[rest], Sb[rest])
+    assert np.array_equal(Ra[rest], Rb[rest])
+    occ = rest & (Sa >= 0)
+    assert np.array_equal(Aa[occ], Ab[occ])
+
+
 @pytest.mark.parametrize("M,batches", [(32, 4), (100, 7)])
 def test_correlator_and_batch_means_error_match_oracle_fp64(M, batches):
     """G(t) and its batch-means error G_err (standard error of the means of
