@@ -309,6 +309,16 @@ int ssp_adjoint_elements_noalloc(ssp_handle* h, const void* rec_dev, const doubl
  * captured graphs.  Used by the autotuner. */
 int ssp_set_mapping(ssp_handle* h, int32_t n_lo, int32_t n_hi, int32_t lanes_per_chain, int32_t beads_per_lane);
 
+/* Launch schedule of the step kernel for ssp_step (the recorded and stored
+ * forwards keep the plain one).  persistent != 0 (the default): as many
+ * workgroups as fit on the device run the launch's steps as units of (time
+ * chunk, wavefront's chains), taken from a queue in the work buffer, a unit
+ * starting once the previous chunk of the same chains has stored their
+ * state, so that no partly filled last round of wavefronts is left; 0: one
+ * wavefront per group of chains for the whole launch.  Trajectories are the
+ * same bit for bit.  Synchronises the device; drops captured graphs. */
+int ssp_set_schedule(ssp_handle* h, int persistent);
+
 /* Kernel timing mode (for measurement): while enabled, ssp_step launches
  * without a graph and brackets the step-kernel launches of every chunk with
  * hipEvents on the caller's stream. */

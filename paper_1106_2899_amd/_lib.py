@@ -44,6 +44,7 @@ EXPORTS = [
     "ssp_adjoint_elements",
     "ssp_adjoint_elements_noalloc",
     "ssp_set_mapping",
+    "ssp_set_schedule",
     "ssp_set_kernel_timing",
     "ssp_kernel_time",
     "ssp_destroy",
@@ -122,6 +123,7 @@ def lib():
             "ssp_adjoint_elements": [vp, vp, vp, i32, i32, vp, vp, vp],
             "ssp_adjoint_elements_noalloc": [vp, vp, vp, i32, i32, vp, vp],
             "ssp_set_mapping": [vp, i32, i32, i32, i32],
+            "ssp_set_schedule": [vp, ctypes.c_int],
             "ssp_set_kernel_timing": [vp, ctypes.c_int],
             "ssp_kernel_time": [vp, f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
             "ssp_destroy": [vp],

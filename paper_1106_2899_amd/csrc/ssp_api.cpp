@@ -70,7 +70,7 @@ bool mapping_supported(int W, int B)
 struct Layout {
     // work buffer offsets (bytes)
     size_t ctrl, flags, off, n, elem, gid, tasks, elem_off, thr, samples, hist, acc, pend, acc_v, pend_v, batch,
-        series, corr_out, total;
+        series, corr_out, sched, total;
     // state buffer offsets
     size_t r0, r1, a0, a1, s, state_total;
     int64_t q_cap;
@@ -229,6 +229,9 @@ Layout make_layout(const Resolved& r)
     L.pend_v = take(cv ? sizeof(double) * (size_t)3 * M * 16 : 0);
     L.batch = take(lv ? sizeof(double) * (size_t)k.corr_batches * lv * 16 : 0);
     L.corr_out = take(lv ? sizeof(double) * (size_t)lv * 16 * 2 : 0);
+    // persistent schedule: per mapping group a counter and a word per wave task
+    // (at most M + 8 words), zeroed as (M + 17) / 2 doubles
+    L.sched = take(sizeof(uint32_t) * (size_t)(M + 18));
     L.series = take(sizeof(double) * (size_t)k.n_elements * k.series_capacity * 6);
     L.total = o;
     const size_t beads = (size_t)r.total_beads;
@@ -275,6 +278,7 @@ struct ssp_handle {
     std::map<std::pair<int64_t, const double*>, hipGraphExec_t> graphs;
     std::string err;
     std::string warning;  // set at creation (cap_warning)
+    bool persistent = true;  // plain steps run the persistent schedule (ssp_set_schedule)
     // device address of the static scratch of the allocation-free reverse
     // pass, looked up at creation (null if the lookup failed; hipError kept)
     double* noalloc = nullptr;
@@ -355,6 +359,10 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
     const int64_t M = k.n_chains;
     for (int64_t done = 0; done < n;) {
         const int32_t m = (int32_t)std::min<int64_t>(h->lay.chunk, n - done);
+        // a plain step (nothing recorded or stored) runs the persistent schedule
+        const bool persistent = !rec_s && !ck_end && !out && h->persistent;
+        uint32_t* sched = reinterpret_cast<uint32_t*>(h->work + h->lay.sched);
+        if (persistent) HIPCHK(h, launch_zero(reinterpret_cast<double*>(sched), (M + 16 + 1) / 2, s));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (h->timing) {
             HIPCHK(h, hipEventCreate(&e0));
@@ -363,6 +371,13 @@ int enqueue_steps(ssp_handle* h, int64_t n, const double* kappa, hipStream_t s, 
         }
         for (auto& g : h->groups) {
             StepArgs a{};
+            if (persistent) {  // each group's counter and progress words after the previous group's
+                const int64_t cpw = kWaveSize / g.first.W;
+                a.n_wave_tasks = (g.second.second + cpw - 1) / cpw;
+                a.sched = sched;
+                sched += 1 + a.n_wave_tasks;
+                a.chunk = m;  // the launcher picks the chunk length
+            }
             a.st = h->st();
             a.ct = h->ct();
             a.tasks = reinterpret_cast<const int32_t*>(h->work + h->lay.tasks) + g.second.first;
@@ -1120,6 +1135,19 @@ int ssp_set_mapping(ssp_handle* h, int32_t n_lo, int32_t n_hi, int32_t lanes_per
     HIPCHK(h, hipMemcpy(h->work + h->lay.tasks, tasks.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
+    return SSP_OK;
+}
+
+int ssp_set_schedule(ssp_handle* h, int persistent)
+{
+    if (!h) return SSP_EINVAL;
+    if ((persistent != 0) != h->persistent) {
+        HIPCHK(h, hipSetDevice(h->device));
+        HIPCHK(h, hipDeviceSynchronize());
+        for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+        h->persistent = persistent != 0;
+    }
     return SSP_OK;
 }
 

@@ -93,6 +93,13 @@ struct StepArgs {
     void* traj2;
     void* dlog;
     int64_t* dcnt;
+    // Persistent schedule (plain step launches only; null: one wavefront per
+    // wave task for the whole launch): sched[0] the unit counter, sched[1 +
+    // w] the chunks of wave task w finished, all zero at launch; chunk: steps
+    // per unit; n_wave_tasks: wavefronts' worth of tasks.
+    uint32_t* sched;
+    int32_t chunk;
+    int64_t n_wave_tasks;
     int32_t dcap;
 };
 

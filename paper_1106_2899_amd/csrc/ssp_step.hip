@@ -31,6 +31,8 @@
 // k_replay is the same step with the slot decisions of 3 and 4 read from a
 // recording: the adjoint's reverse pass re-creates each checkpoint segment's
 // positions with it.
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "ssp_device.h"
@@ -146,7 +148,7 @@ template <typename T, int B, bool SAMP> struct WaveLds {
 // run at rest (no table) uses the variant without them, whose registers are
 // not shared with the flow code.  The two give identical trajectories at
 // kappa = 0.
-template <typename T, int W, int B, bool K1, bool RP, bool ST, bool FL>
+template <typename T, int W, int B, bool K1, bool RP, bool ST, bool FL, bool PS>
 __device__ __forceinline__ void step_body(const StepArgs& a)
 {
     constexpr bool kComp = std::is_same<T, float>::value;  // (hi, lo) position sums
@@ -164,7 +166,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     const int li = lane % W;
     const int seg = lane / W;
     const int sb = lane - li;  // first lane of the segment
-    const int64_t task = ((int64_t)blockIdx.x * kWavesPerGroup + wv) * kChainsPerWave + seg;
+
+    // One unit of work: the chains of wave task `wtask` for n_steps steps from
+    // global step g0, their samples from index q0 of the launch's sample
+    // buffer on.  State is read from HBM at the start and written back at the
+    // end, so units of one wave task may run on different wavefronts.
+    auto run = [&](const int64_t wtask, const int64_t g0, const int32_t n_steps, const int64_t q0) {
+    const int64_t task = wtask * kChainsPerWave + seg;
     const bool valid = task < a.n_tasks;
     const int chain = valid ? a.tasks[task] : 0;
     const int n = valid ? a.ct.n[chain] : 0;
@@ -277,7 +285,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     bonds_and_records();
     refresh_offsets();
 
-    const int64_t g0 = a.ctrl[kCtrlSteps];
 
     // Trajectory output: R after every step (row 0: the state before the
     // first step), FP32 positions rounded from hi + lo.  Anchors are written
@@ -363,7 +370,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     }
     // sampling phase: step g is sampled when (g + 1) % sample_every == 0
     int phase = a.sample_every > 0 ? (int)((g0 + 1) % a.sample_every) : 1;
-    int64_t q_launch = 0;  // samples already written by this launch
+    int64_t q_launch = q0;  // index in the launch's sample buffer of this unit's next sample
 
     // Replay: the recorded slot row of a step is loaded one step ahead, so that
     // its latency runs under the previous step.
@@ -376,15 +383,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         }
     };
     if constexpr (RP) {
-        if (a.n_steps > 0) replay_load(g0, replay_ahead);
+        if (n_steps > 0) replay_load(g0, replay_ahead);
     }
 
-    for (int step = 0; step < a.n_steps; ++step) {
+    for (int step = 0; step < n_steps; ++step) {
         const int64_t g = g0 + step;
         if constexpr (RP) {
 #pragma unroll
             for (int b = 0; b < B; ++b) replay_next[b] = replay_ahead[b];
-            if (step + 1 < a.n_steps) replay_load(g + 1, replay_ahead);
+            if (step + 1 < n_steps) replay_load(g + 1, replay_ahead);
         }
         const bool even = (g & 1) == 0;  // wave-uniform
         const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
@@ -814,7 +821,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     if constexpr (RP) {
 #pragma unroll
         for (int b = 0; b < B; ++b)
-            if (li * B + b < n) store_a(a.n_steps, b);
+            if (li * B + b < n) store_a(n_steps, b);
     }
     if constexpr (ST) {
 #pragma unroll
@@ -823,6 +830,55 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         if (valid && li == 0) a.dcnt[chain] = dcount;
     }
     if (!finite_ok) atomicOr(a.flags, kFlagNonFinite);
+    };  // run
+
+    if constexpr (PS) {
+        static_assert(!RP && !ST, "the persistent schedule runs plain steps only");
+        {
+            // Persistent schedule (a plain step launch): the units (time chunk
+            // c, wave task w) are taken in the order c * n_wt + w from one
+            // counter, and a unit waits until unit (c - 1, w) has stored its
+            // chains' state.  Every unit's predecessor was taken earlier, by a
+            // wavefront that is running, and the earliest unfinished unit
+            // never waits, so the queue drains; all wavefronts stay busy to
+            // the end instead of the last round of a one-wave-per-task launch
+            // running part-full.
+            const int64_t g0 = a.ctrl[kCtrlSteps];
+            const int64_t n_wt = a.n_wave_tasks;
+            const int32_t L = a.chunk;
+            const int64_t n_chunks = (a.n_steps + L - 1) / L;
+            const int64_t total = n_wt * n_chunks;
+            uint32_t* progress = a.sched + 1;  // [n_wt] chunks finished per wave task
+            for (;;) {
+                uint32_t u = 0;
+                if (lane == 0) u = atomicAdd(a.sched, 1u);
+                u = __builtin_amdgcn_readfirstlane(u);
+                if ((int64_t)u >= total) break;
+                const int64_t c = (int64_t)u / n_wt, w = (int64_t)u % n_wt;
+                if (c > 0) {
+                    // bounded wait (the bound only guards against a hang: the
+                    // predecessor is running and finishes within one unit)
+                    for (uint32_t spin = 0;; ++spin) {
+                        const uint32_t done = __hip_atomic_load(&progress[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        if (__builtin_amdgcn_readfirstlane(done) >= (uint32_t)c) break;
+                        if (spin > (1u << 22)) {
+                            if (lane == 0) atomicOr(a.flags, kFlagInternal);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+                const int64_t gs = g0 + c * L;
+                const int32_t ns = (int32_t)min((int64_t)L, (int64_t)a.n_steps - c * L);
+                // samples of steps g0 .. gs - 1 precede this unit's: steps g with (g + 1) % n_s == 0
+                const int64_t q0 = a.sample_every > 0 ? gs / a.sample_every - g0 / a.sample_every : 0;
+                run(w, gs, ns, q0);
+                __hip_atomic_store(&progress[w], (uint32_t)(c + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    } else {
+        run((int64_t)blockIdx.x * kWavesPerGroup + wv, a.ctrl[kCtrlSteps], a.n_steps, 0);
+    }
 }
 
 // Waves per SIMD the register budget must allow.  The step is held one wave
@@ -841,7 +897,17 @@ template <typename T, int W, int B, bool K1, bool ST, bool FL>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>)))
 k_step(StepArgs a)
 {
-    step_body<T, W, B, K1, false, ST, FL>(a);
+    step_body<T, W, B, K1, false, ST, FL, false>(a);
+}
+
+// The same step under the persistent schedule (plain steps: nothing recorded
+// or stored), a kernel of its own so that the queue's registers do not weigh
+// on the other variants.
+template <typename T, int W, int B, bool K1, bool FL>
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEu<T, B>)))
+k_step_queue(StepArgs a)
+{
+    step_body<T, W, B, K1, false, false, FL, true>(a);
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
@@ -852,11 +918,56 @@ template <typename T, int W, int B, bool FL>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && B == 1 ? 6 : 1)))
 k_replay(StepArgs a)
 {
-    step_body<T, W, B, false, true, false, FL>(a);
+    step_body<T, W, B, false, true, false, FL, false>(a);
+}
+
+// Workgroups of the queue kernel that fit on the device at once (occupancy x
+// CUs), looked up once per kernel.
+template <typename T, int W, int B, bool K1, bool FL> int resident_groups()
+{
+    static int cached = 0;
+    if (cached == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_queue<T, W, B, K1, FL>, kGroupThreads, 0) !=
+                hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached = per_cu * cus;
+    }
+    return cached;
 }
 
 template <typename T, int W, int B, bool FL> hipError_t launch_f(const StepArgs& a, dim3 grid, hipStream_t s)
 {
+    if (a.sched && !a.replay_s && !a.traj) {
+        // persistent: as many groups as fit, each wave taking units from the queue
+        auto kern = a.construct_rule == 1 ? k_step_queue<T, W, B, true, FL> : k_step_queue<T, W, B, false, FL>;
+        const int r = a.construct_rule == 1 ? resident_groups<T, W, B, true, FL>() : resident_groups<T, W, B, false, FL>();
+        StepArgs p = a;
+        // time chunks per wave task: the count (1..16, chunks of >= 64 steps)
+        // whose last round of units leaves the fewest wavefront slots idle,
+        // plus a small charge per chunk for re-reading and writing the state
+        const double slots = (double)std::max(1, r) * kWavesPerGroup;
+        int best = 1;
+        double best_loss = 1e30;
+        for (int nc = 1; nc <= 16; ++nc) {
+            if (nc > 1 && (a.n_steps + nc - 1) / nc < 64) break;
+            const double rounds = (double)(a.n_wave_tasks * nc) / slots;
+            const double loss = (std::ceil(rounds) - rounds) / std::ceil(rounds) + 0.002 * nc;
+            if (loss < best_loss - 1e-12) {
+                best_loss = loss;
+                best = nc;
+            }
+        }
+        p.chunk = (a.n_steps + best - 1) / best;
+        if (p.chunk < 1) p.chunk = 1;
+        const int64_t units = a.n_wave_tasks * ((a.n_steps + p.chunk - 1) / p.chunk);
+        const int64_t need = (units + kWavesPerGroup - 1) / kWavesPerGroup;
+        const dim3 pg((unsigned)std::max<int64_t>(1, std::min<int64_t>(r > 0 ? r : need, need)));
+        hipLaunchKernelGGL(kern, pg, dim3(kGroupThreads), 0, s, p);
+        return hipGetLastError();
+    }
     if (a.replay_s)
         hipLaunchKernelGGL((k_replay<T, W, B, FL>), grid, dim3(kGroupThreads), 0, s, a);
     else if (a.traj && a.construct_rule == 1)

@@ -319,6 +319,11 @@ class Ensemble:
         self._chk(lib().ssp_set_mapping(self._h, int(n_lo), int(n_hi), int(lanes_per_chain), int(beads_per_lane)))
         return self
 
+    def set_schedule(self, persistent: bool) -> "Ensemble":
+        """Persistent (default) or one-wavefront-per-task schedule of ssp_step."""
+        self._chk(lib().ssp_set_schedule(self._h, 1 if persistent else 0))
+        return self
+
     def set_kernel_timing(self, enable: bool) -> "Ensemble":
         self._chk(lib().ssp_set_kernel_timing(self._h, 1 if enable else 0))
         return self

@@ -64,6 +64,34 @@ def test_chunking_and_graph_invariance_bitwise():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("steps", [1, 7, 300, 2000])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_persistent_schedule_equals_plain_launches_bitwise(precision, steps):
+    """ssp_step under the persistent schedule (time chunks of wavefronts'
+    chains taken from a queue) and under one wavefront per chain group give
+    the same state, correlator and element series bit for bit: mixed lengths
+    (several mapping groups), mixed flows, sampling every 3 steps, and launch
+    lengths from one step (one chunk) to several chunks."""
+    N = [8, 16, 24, 32, 64, 100] * 40
+    M = len(N)
+    offs = np.array([0, M // 3, 2 * M // 3, M])
+    kap = np.zeros((3, 9))
+    kap[0, 1] = 0.4
+    kap[1, [0, 4, 8]] = [0.02, -0.01, -0.01]
+    kw = dict(precision=precision, seed=29, sample_every=3, corr_levels=8, corr_batches=4, series_capacity=1000,
+              n_elements=3, element_offsets=offs, max_steps_per_launch=max(1, steps))
+    a = _ens(N, **kw).init()
+    b = _ens(N, **kw).init()
+    b.set_schedule(False)
+    for e in (a, b):
+        e.step(steps, kap)
+        e.step(steps)
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)
+    assert np.array_equal(a.correlator()["G"], b.correlator()["G"])
+    assert torch.equal(a.element_series(), b.element_series())
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_run_at_rest_equals_a_zero_velocity_gradient_table_bitwise(precision):
     """ssp_step with no table (the variant compiled without the flow terms)
