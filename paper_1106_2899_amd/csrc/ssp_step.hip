@@ -387,6 +387,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     }
 
     for (int step = 0; step < n_steps; ++step) {
+        // the flow terms test the bits of kmask every step; recomputing those
+        // tests (scalar ops) is cheaper than keeping nine hoisted conditions
+        // in scalar registers across the loop, which spilled
+        if constexpr (FL) asm volatile("" : "+s"(kmask));
         const int64_t g = g0 + step;
         if constexpr (RP) {
 #pragma unroll

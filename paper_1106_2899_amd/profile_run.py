@@ -1,6 +1,8 @@
 """Short, fixed GPU runs for rocprofv3 (kernel trace and counter passes).
 
     python -m paper_1106_2899_amd.profile_run step   # step kernel, 16384 x N=32, 3 launches of 5000 steps
+    python -m paper_1106_2899_amd.profile_run flow   # the same ensemble under simple shear (rate 1) and under
+                                                     # uniaxial elongation (rate 0.05), 2 launches of 2000 steps each
     python -m paper_1106_2899_amd.profile_run copy   # 1 GiB read + 1 GiB write elementwise copy (counter calibration)
     python -m paper_1106_2899_amd.profile_run adjoint  # 65536 x N=64 under shear 0.01: forward, recorded forward, reverse
     python -m paper_1106_2899_amd.profile_run adjoint_stored  # the same window as one stored segment (no replay)
@@ -22,6 +24,22 @@ def step(launches: int = 3, md_steps: int = 5000) -> None:
         e.step(md_steps)
     torch.cuda.synchronize()
     print("step launches:", launches, "bead-steps per launch:", 16384 * 32 * md_steps, flush=True)
+
+
+def flow(launches: int = 2, md_steps: int = 2000) -> None:
+    from .ensemble import Ensemble
+
+    for name, kap in (("shear 1.0", [0, 1.0, 0, 0, 0, 0, 0, 0, 0]),
+                      ("elongation 0.05", [0.05, 0, 0, 0, -0.025, 0, 0, 0, -0.025])):
+        e = Ensemble(32, 16384, precision="fp32", seed=2, sample_every=10, corr_levels=16, corr_batches=16,
+                     max_steps_per_launch=md_steps, use_graph=False)
+        e.init()
+        k = torch.tensor(kap, dtype=torch.float64, device="cuda").reshape(1, 9)
+        for _ in range(launches):
+            e.step(md_steps, k)
+        torch.cuda.synchronize()
+        e.close()
+        print("flow", name, "launches:", launches, "bead-steps per launch:", 16384 * 32 * md_steps, flush=True)
 
 
 def adjoint(chains: int = 65536, beads: int = 64, window: int = 2000, ckpt: int = 100, rate: float = 0.01) -> None:
@@ -53,4 +71,4 @@ def copy(nbytes: int = 1 << 30) -> None:
 
 
 if __name__ == "__main__":
-    {"step": step, "copy": copy, "adjoint": adjoint, "adjoint_stored": adjoint_stored}[sys.argv[1]]()
+    {"step": step, "flow": flow, "copy": copy, "adjoint": adjoint, "adjoint_stored": adjoint_stored}[sys.argv[1]]()
