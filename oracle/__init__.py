@@ -69,6 +69,7 @@ def lib():
         L.ssp_oracle_multitau.argtypes = [ctypes.c_int64, f64p, f64p, ctypes.c_int, ctypes.c_int, f64p, i64p]
         L.ssp_oracle_threads.argtypes = []
         L.ssp_oracle_threads.restype = ctypes.c_int
+        L.ssp_oracle_set_threads.argtypes = [ctypes.c_int]
         L.ssp_oracle_step_forced.argtypes = [ctypes.c_int, i32p, i64p, i64p, f64p, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_uint64, ctypes.c_int64, f64p, f64p, i32p, i32p]
         L.ssp_oracle_adjoint.argtypes = [ctypes.c_int, i32p, i64p, i64p, f64p, ctypes.c_double, ctypes.c_double,
@@ -89,6 +90,11 @@ def philox(counter, key):
     out = np.zeros(4, dtype=np.uint32)
     lib().ssp_oracle_philox(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(out, ctypes.c_uint32))
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads (OpenMP) of the oracle's later calls."""
+    lib().ssp_oracle_set_threads(int(n))
 
 
 def threads() -> int:

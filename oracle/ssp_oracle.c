@@ -65,6 +65,10 @@
 /* Threads the OpenMP loops over chains use. */
 int ssp_oracle_threads(void) { return omp_get_max_threads(); }
 
+/* Threads of the later parallel loops (the benchmark times the oracle on one
+ * thread and on all of them). */
+void ssp_oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif

@@ -14,6 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libssp.so")
+PROBE_LIB = os.path.join(PKG, "libssp_probe.so")  # VALU issue-cost probe (measurement only)
 
 SOURCES = ["ssp_step.hip", "ssp_aux.hip", "ssp_adjoint.hip", "ssp_moduli.hip", "ssp_api.cpp"]
 HEADERS = ["ssp_device.h", "ssp_internal.h"]
@@ -58,6 +59,12 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd, cwd=tmp)
         os.replace(out_tmp, LIB)
+        cmd = [cc, *COMMON, "-x", "hip", *DEVICE_FLAGS, "-shared", "-o", PROBE_LIB + ".tmp",
+               os.path.join(CSRC, "issue_probe.hip")]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd, cwd=tmp)
+        os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 

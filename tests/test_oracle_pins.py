@@ -428,23 +428,69 @@ def test_n2_stationary_law_of_z_cpu_rule_and_detailed_balance_comparison():
 
 # ---------------------------------------- equilibrium with springs on ------
 
-def test_springs_on_equilibrium_laws_small_dt_bias():
-    """With springs on, the stationary state of the scheme approaches the
-    equilibrium of Sec. 2.1 (Poisson Z of mean N/N0, uniform S, anchor
-    offsets of variance N_s/3, bonds of variance 1/3) up to O(dt)."""
-    N, M = 8, 4096
-    e = oracle.Ensemble([N] * M, seed=41).init()
-    e.run(1500, keep_samples=False)
-    S = e.S.reshape(M, N)
-    Z = (S >= 0).sum(axis=1)
-    assert Z.mean() == pytest.approx(N / N0, rel=0.03)
-    cnt = np.bincount(S[S >= 0], minlength=N) / (S >= 0).sum()
-    np.testing.assert_allclose(cnt, 1.0 / N, atol=0.02)
-    d = e.anchor_offsets()
-    d = d[~np.isnan(d[:, 0])]
-    assert d.var() == pytest.approx(NS / 3.0, rel=0.06)
-    R = e.R.reshape(M, N, 3)
-    assert (R[:, 1:] - R[:, :-1]).var() == pytest.approx(1.0 / 3.0, rel=0.06)
+def _stationary_averages(N, M, dt, seed, t_eq=10.0, t_avg=20.0, every=0.25):
+    """Time averages over [t_eq, t_eq + t_avg] (snapshots every `every` time
+    units) of the per-chain observables, with standard errors over the
+    independent chains: <Z>, the bond variance per component, the
+    anchor-offset variance per component, and the share of springs on an end
+    bead (the last two as ratio estimators)."""
+    e = oracle.Ensemble([N] * M, dt=dt, seed=seed).init()
+    e.run(int(round(t_eq / dt)), keep_samples=False)
+    k, nsnap = int(round(every / dt)), int(round(t_avg / every))
+    z, b2, d2, nd, ends, occn = (np.zeros(M) for _ in range(6))
+    for _ in range(nsnap):
+        e.run(k, keep_samples=False)
+        S, R, A = e.S.reshape(M, N), e.R.reshape(M, N, 3), e.A.reshape(M, N, 3)
+        occ = S >= 0
+        z += occ.sum(axis=1)
+        b2 += ((R[:, 1:] - R[:, :-1]) ** 2).mean(axis=(1, 2))
+        RS = np.take_along_axis(R, np.where(occ, S, 0)[..., None], axis=1)
+        d2 += (np.where(occ[..., None], RS - A, 0.0) ** 2).sum(axis=(1, 2))
+        nd += 3 * occ.sum(axis=1)
+        ends += (occ & ((S == 0) | (S == N - 1))).sum(axis=1)
+        occn += occ.sum(axis=1)
+
+    def mean_se(x):
+        x = x / nsnap
+        return x.mean(), x.std(ddof=1) / math.sqrt(M)
+
+    def ratio_se(s, c):
+        r = s.sum() / c.sum()
+        return r, math.sqrt(((s - r * c) ** 2).sum() * M / (M - 1)) / c.sum()
+
+    return {"Z": mean_se(z), "bond_var": mean_se(b2), "offset_var": ratio_se(d2, nd), "end_share": ratio_se(ends, occn)}
+
+
+@pytest.mark.parametrize("N", [3, 8])
+def test_springs_on_equilibrium_laws_extrapolate_in_dt(N):
+    """With springs on, the stationary state of the scheme at dt = 0.01,
+    0.005, 0.0025 differs from the equilibrium of Sec. 2.1 by a bias linear in
+    dt, whose extrapolation to dt = 0 gives that equilibrium within 3 sigma:
+    Z Poisson of mean N/N0 truncated at the capacity C = N (mean
+    sum z p_z / sum p_z, p_z = lam^z / z!), spring positions uniform over the
+    beads (share 2/N on the end beads), anchor offsets of variance N_s/3 and
+    bonds of variance 1/3 per component.  The Euler-Maruyama bond-variance
+    bias is positive (the discrete Ornstein-Uhlenbeck variance exceeds the
+    continuous one by a factor 1 + k dt / 2 + O(dt^2)) and resolved."""
+    M = 4096
+    lam = N / N0
+    p = np.array([lam ** z / math.factorial(z) for z in range(N + 1)])
+    exact = {"Z": float((np.arange(N + 1) * p).sum() / p.sum()), "bond_var": 1.0 / 3.0,
+             "offset_var": NS / 3.0, "end_share": 2.0 / N}
+    dts = np.array([0.01, 0.005, 0.0025])
+    res = [_stationary_averages(N, M, dt, seed=41 + N) for dt in dts]
+    X = np.stack([np.ones(3), dts], axis=1)
+    for key, want in exact.items():
+        y = np.array([r[key][0] for r in res])
+        s = np.array([r[key][1] for r in res])
+        W = np.diag(1.0 / s ** 2)
+        cov = np.linalg.inv(X.T @ W @ X)
+        a, b = cov @ X.T @ W @ y
+        chi2 = float((((y - (a + b * dts)) / s) ** 2).sum())
+        assert stats.chi2.sf(chi2, 1) > 1e-3, (key, y, s, chi2)  # linear in dt
+        assert abs(a - want) <= 3.0 * math.sqrt(cov[0, 0]), (key, a, math.sqrt(cov[0, 0]), want)
+        if key == "bond_var":
+            assert b > 5.0 * math.sqrt(cov[1, 1]), (b, math.sqrt(cov[1, 1]))
 
 
 # --------------------------------------------- linear response (Sec. 2.3) ----
