@@ -46,33 +46,40 @@ def _log(msg):
 
 
 def algorithmic_valu_slots(sample_every: int = SAMPLE_EVERY, n0: float = 4.0, flow_entries: float = 0.0) -> float:
-    """VALU lane-issue slots per bead-step that the method needs on this
-    workload, each operation weighted by its issue cost measured on gfx950
-    with a throughput probe (full rate = 1, which includes the 32x32->64
-    integer multiply, the three-input bitop and FP64 FMA; FP32
-    transcendentals log/exp/sin/cos/sqrt/rcp = 2), in the arithmetic the path
-    requires (compensated FP32 positions) and with the random stream at its
-    minimum of five words per bead-step:
+    """VALU issue slots per bead-step that the method needs on this workload.
+    A slot is one wave64 instruction issued over 4 SIMD cycles (16 lanes per
+    cycle), so the chip's peak is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+    lane-slots/s.  Each operation is weighted by its issue cost measured on
+    gfx950 with the probe library (SIMD cycles per wave64 instruction / 4):
+    0.5 for FP32 add/sub/mul/FMA, 32-bit integer add/sub, and/or/xor, the
+    three-input bitop, v_mov and right shifts; 1 for the 32x32->64 integer
+    multiply-add, compares, selects, min/max, alignbit, conversions, DPP
+    moves and FP64 add/mul/FMA; 2 for the FP32 transcendentals log, exp,
+    sqrt, sin, cos and rcp.  The arithmetic is the path's (compensated FP32
+    positions, FP64 stress) with the random stream at its minimum of five
+    words per bead-step:
       random words: 1.5 Box-Muller pairs (3 words) + hop + reconstruction
-        = 1.25 Philox4x32-10 blocks x 10 rounds x (2 products + 2 xors)  ->  50
-      Box-Muller, 1.5 pairs x (2 uniforms x 2, log 2, mul, sqrt 2,
-        sin 2, cos 2, 2 mul)                                           ->  22.5
-      bonds from compensated positions, 3 x 3                          ->   9
-      move: bond-force difference 3, two FMAs per component 6,
-        compensated position update 12                                 ->  21
-      spring-force gather, 3 adds per spring                           ->   3 / N_0
-      hop per occupied slot: post-move offset 3, two energy
-        differences 12, two probabilities 2 x 8, decision 5            ->  36 / N_0
-      reconstruction word test                                         ->   2
-      anchor offsets for the next step (compensated), per spring      ->   9 / N_0
+        = 1.25 Philox4x32-10 blocks x 10 rounds x (2 multiply-adds
+        + 2 three-input xors)                                           ->  37.5
+      Box-Muller, 1.5 pairs x (2 uniforms x (alignbit + add) 3, log 2,
+        mul 0.5, sqrt 2, sin 2, cos 2, 2 mul 1)                         ->  18.75
+      bonds from compensated positions, 3 x (2 sub + add)               ->   4.5
+      move: bond-force difference 1.5, two FMAs per component 3,
+        compensated position update 12 x 0.5                            ->  10.5
+      spring-force gather, 3 adds per spring                            ->   1.5 / N_0
+      hop per occupied slot: post-move offset 1.5, two energy
+        differences 2 x 3, two probabilities 2 x (mul, exp, add, rcp,
+        mul, min) 13, decision 3.5                                      ->  24 / N_0
+      reconstruction word test (one compare)                            ->   1
+      anchor offsets for the next step (compensated), per spring       ->   4.5 / N_0
       stress and virtual stress (FP64), per sample: per bead 3 cvt
-        + 6 FMA, per spring the same                                   ->  (9 + 9 / N_0) / n_s
-    Under flow, one FMA per nonzero entry of kappa for every bead and for
-    every spring's anchor: flow_entries (1 + 1 / N_0) (flow_entries: nonzero
-    entries of kappa, averaged over the beads).
+        + 6 FMA, per spring the same                                    ->  (9 + 9 / N_0) / n_s
+    Under flow, one FP32 FMA per nonzero entry of kappa for every bead and
+    every spring's anchor: 0.5 flow_entries (1 + 1 / N_0) (flow_entries:
+    nonzero entries of kappa, averaged over the beads).
     """
-    return (50.0 + 22.5 + 9.0 + 21.0 + 3.0 / n0 + 36.0 / n0 + 2.0 + 9.0 / n0 + (9.0 + 9.0 / n0) / sample_every
-            + flow_entries * (1.0 + 1.0 / n0))
+    return (37.5 + 18.75 + 4.5 + 10.5 + 1.5 / n0 + 24.0 / n0 + 1.0 + 4.5 / n0 + (9.0 + 9.0 / n0) / sample_every
+            + 0.5 * flow_entries * (1.0 + 1.0 / n0))
 
 
 # The step kernel's source and the headers it is compiled with.

@@ -17,6 +17,7 @@
 //   dJ/dR_m     = lR + dt (L lR - (3/N_s) c lR + kappa^T lR),
 // L the free-end bond Laplacian (stiffness 3) and c the springs per bead.
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "ssp_device.h"
@@ -198,11 +199,23 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
 #pragma unroll
     for (int q = 0; q < 9; ++q) G[q] = 0.0;
     double Gns = 0.0;
+    // The per-step gradient terms dt (lR (x) R_m + lA (x) A_m) and
+    // dt (3/N_s^2) lR[S_m] . (R_m[S_m] - A_m) are summed in the path's
+    // precision over blocks of kBlock steps (without the constant factors),
+    // and each block's sums are added to the FP64 totals: a block's sum holds
+    // at most 2 kBlock rounding errors of its own size, and the conversions
+    // and FP64 arithmetic run once per block instead of once per step.
+    constexpr int kBlock = 16;
+    T Gp[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Gp[q] = T(0);
+    T Gnsp = T(0);
+    int in_block = 0;
 
     // Step m reads the slot rows m and m + 1 and the trajectory row m.  Row
     // m + 1 of the slots is row m of the step after, carried; row m and the
-    // trajectory are loaded one step ahead, so that their latency runs under
-    // the previous step's arithmetic.
+    // trajectory are loaded kAhead steps ahead, so that their latency runs
+    // under the arithmetic of the steps before.
     // Recorded slot rows are checked before use as LDS indices (where they are
     // used, not where they are loaded, so that a prefetch is not waited for):
     // a value outside -1..n-1 reads as an empty slot and latches kFlagReplay.
@@ -218,18 +231,21 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         return ok ? v : -1;
     };
     auto row_at = [&](int64_t r, int i) -> int { return checked(a.rec_s[r * a.total + off + i]); };
-    int s_next[B], s_pre[B];
-    v3<T> R_pre[B];
-    auto prefetch = [&](int m) {
+    // rows in flight: ring slot q holds the rows len - 1 - q - kAhead k
+    constexpr int kAhead = 3;
+    int s_next[B], s_pre[kAhead][B];
+    v3<T> R_pre[kAhead][B];
+    // The loads are unconditional (a row before the window reads row 0, a
+    // lane past the chain's end its first bead) and lanes past the end are
+    // masked where the values are used: a load whose result is merged with
+    // a default would be waited for at once.
+    auto prefetch = [&](int q, int m) {
+        const int row = m > 0 ? m : 0;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int i = li * B + b;
-            s_pre[b] = -1;
-            R_pre[b] = zero3<T>();
-            if (i < n) {
-                s_pre[b] = a.rec_s[(a.m0 + m) * a.total + off + i];  // checked when used
-                R_pre[b] = traj_r(m, i);
-            }
+            const int i = li * B + b < n ? li * B + b : 0;
+            s_pre[q][b] = a.rec_s[(a.m0 + row) * a.total + off + i];  // checked when used
+            R_pre[q][b] = traj_r(row, i);
         }
     };
     v3<double> Ac[B];  // A_{m+1} of the springs alive after step m
@@ -250,9 +266,14 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     }
     const v3<T>* dlog = SW ? reinterpret_cast<const v3<T>*>(a.dlog) + (int64_t)chain * a.dcap : nullptr;
     const uint64_t segm = W == kWaveSize ? ~0ull : (((1ull << W) - 1ull) << sb);
-    if (a.len > 0) prefetch(a.len - 1);
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) prefetch(q, a.len - 1 - q);
 
-    for (int m = a.len - 1; m >= 0; --m) {
+    // One step of the reverse recursion; row m sits in ring slot QC::value.
+    // The loop below is unrolled over the ring, so that no register of a load
+    // still in flight is copied (a copy would wait for the load).
+    auto step_back = [&](const int m, auto QC) {
+        constexpr int qs = decltype(QC)::value;
         const int64_t mg = a.m0 + m;
         int sm[B], s1[B];
         v3<T> Rm[B], Am[B];
@@ -260,7 +281,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         bool cr[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            sm[b] = checked(s_pre[b]);
+            sm[b] = li * B + b < n ? checked(s_pre[qs][b]) : -1;
             s1[b] = s_next[b];
             s_next[b] = sm[b];
             if (SW || m == 0)
@@ -304,7 +325,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            Rm[b] = R_pre[b];
+            Rm[b] = R_pre[qs][b];
             cr[b] = sm[b] < 0 && s1[b] >= 0;
             any_cr |= cr[b];
             Am[b] = zero3<T>();
@@ -321,7 +342,6 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
                 Am[b] = {T(Ac[b].x), T(Ac[b].y), T(Ac[b].z)};
             }
         }
-        if (m > 0) prefetch(m - 1);
         // created springs: their anchor depends on the end bead after the move
         if (__ballot(any_cr) != 0) {
 #pragma unroll
@@ -382,15 +402,15 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             nA[b] = zero3<T>();
             if (sm[b] >= 0) {
                 const v3<T> dd = RS - Am[b];
-                Gns += kns * ((double)lRS.x * dd.x + (double)lRS.y * dd.y + (double)lRS.z * dd.z);
+                Gnsp += lRS.x * dd.x + lRS.y * dd.y + lRS.z * dd.z;
                 if (s1[b] >= 0) {
                     nA[b] = lA[b] + dt * kT(kap, lA[b]);
-                    const double la[3] = {lA[b].x, lA[b].y, lA[b].z};
-                    const double am[3] = {Am[b].x, Am[b].y, Am[b].z};
+                    const T la[3] = {lA[b].x, lA[b].y, lA[b].z};
+                    const T am[3] = {Am[b].x, Am[b].y, Am[b].z};
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) G[3 * p + q] += ddt * la[p] * am[q];
+                        for (int q = 0; q < 3; ++q) Gp[3 * p + q] += la[p] * am[q];
                 }
                 nA[b] = nA[b] + (dt * ks) * lRS;
             }
@@ -408,12 +428,12 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             if (i < n - 1) lap = lap + T(3) * (right - lR[b]);
             if (i > 0) lap = lap - T(3) * (lR[b] - left);
             if (i < n) {
-                const double lr[3] = {lR[b].x, lR[b].y, lR[b].z};
-                const double rm[3] = {Rm[b].x, Rm[b].y, Rm[b].z};
+                const T lr[3] = {lR[b].x, lR[b].y, lR[b].z};
+                const T rm[3] = {Rm[b].x, Rm[b].y, Rm[b].z};
 #pragma unroll
                 for (int p = 0; p < 3; ++p)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) G[3 * p + q] += ddt * lr[p] * rm[q];
+                    for (int q = 0; q < 3; ++q) Gp[3 * p + q] += lr[p] * rm[q];
                 nR[b] = lR[b] + dt * (lap - (ks * T(c[b])) * lR[b] + kT(kap, lR[b]));
             } else {
                 nR[b] = zero3<T>();
@@ -424,8 +444,30 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
             lR[b] = nR[b];
             lA[b] = nA[b];
         }
+        if (++in_block == kBlock || m == 0) {  // wave-uniform
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                G[q] += ddt * (double)Gp[q];
+                Gp[q] = T(0);
+            }
+            Gns += kns * (double)Gnsp;
+            Gnsp = T(0);
+            in_block = 0;
+        }
+        // row m - kAhead into this step's ring slot, issued after the last
+        // use of row m, so that the load can reuse its registers
+        prefetch(qs, m - kAhead);
         wave_sync();
+    };
+    static_assert(kAhead == 3, "the loop below is unrolled over a ring of three rows");
+    int m = a.len - 1;
+    for (; m >= 2; m -= 3) {  // rows m, m - 1, m - 2 in ring slots 0, 1, 2
+        step_back(m, std::integral_constant<int, 0>{});
+        step_back(m - 1, std::integral_constant<int, 1>{});
+        step_back(m - 2, std::integral_constant<int, 2>{});
     }
+    if (m >= 0) step_back(m, std::integral_constant<int, 0>{});
+    if (m >= 1) step_back(m - 1, std::integral_constant<int, 1>{});
 
     // N_s dependence of the sampled initial anchors A = R_S + sqrt(N_s/3) g
     if (a.init_terms) {

@@ -71,39 +71,32 @@ def copy(nbytes: int = 1 << 30) -> None:
     print("copy bytes read:", nbytes, "written:", nbytes, flush=True)
 
 
-def issue(iters: int = 4000, waves_per_simd: int = 8) -> None:
-    """Issue cost of each VALU instruction kind of the probe library, in SIMD
-    cycles per wave64 instruction: every SIMD runs `waves_per_simd` waves of
-    32 x iters independent instructions of one kind; the cost is the median
-    over waves of their shader-clock cycles / (waves per SIMD x instructions
-    per wave).  The shader clock's rate is its count over the 100 MHz
-    reference clock's."""
+def issue(iters: int = 16000, waves_per_simd: int = 8) -> None:
+    """One launch per VALU instruction kind of the probe library: every SIMD
+    runs `waves_per_simd` waves of 32 x iters independent instructions of the
+    kind.  Prints the launch times (HIP events) and nanoseconds per
+    instruction and SIMD; the cost in SIMD cycles comes from the same run
+    under rocprofv3 (GRBM_GUI_ACTIVE per XCD over SQ_INSTS_VALU / SIMDs)."""
     import ctypes
     import os
 
     lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "libssp_probe.so"))
     lib.ssp_probe_name.restype = ctypes.c_char_p
-    lib.ssp_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+    lib.ssp_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_float)]
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     blocks = cus * waves_per_simd  # 4 waves per workgroup, 4 SIMDs per CU
     sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
-    clocks = torch.zeros(blocks * 4 * 2, dtype=torch.int64, device="cuda")
     ms = ctypes.c_float()
-    per_wave = 32 * iters
-    print(f"CUs {cus}, {waves_per_simd} waves per SIMD, {per_wave} instructions per wave", flush=True)
-    print("| Instruction | SIMD cycles per wave64 instruction | shader clock GHz | launch ms |")
-    print("|---|---|---|---|")
+    per_simd = 32 * iters * waves_per_simd
+    print(f"CUs {cus}, {waves_per_simd} waves per SIMD, {per_simd} instructions per SIMD", flush=True)
+    print("| Instruction | launch ms | ns per instruction and SIMD |")
+    print("|---|---|---|")
     for op in range(lib.ssp_probe_count()):
         for it in (16, iters):  # a short warm-up launch, then the measured one
-            if lib.ssp_probe_run(op, blocks, it, ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(clocks.data_ptr()),
-                                 ctypes.byref(ms)) != 0:
+            if lib.ssp_probe_run(op, blocks, it, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms)) != 0:
                 raise RuntimeError(f"probe {op} failed")
-        c = clocks.view(-1, 2).cpu().double()
-        cyc = c[:, 0].median().item()
-        ghz = (c[:, 0] / c[:, 1]).median().item() * 0.1
-        print(f"| {lib.ssp_probe_name(op).decode()} | {cyc / (waves_per_simd * per_wave):.3f} | {ghz:.3f} | "
-              f"{ms.value:.3f} |", flush=True)
+        print(f"| {lib.ssp_probe_name(op).decode()} | {ms.value:.3f} | {ms.value * 1e6 / per_simd:.3f} |", flush=True)
 
 
 if __name__ == "__main__":
