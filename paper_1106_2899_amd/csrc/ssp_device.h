@@ -209,6 +209,16 @@ __device__ __forceinline__ void cadd3(v3<float>& hi, v3<float>& lo, v3<float> in
     cadd(hi.z, lo.z, inc.z);
 }
 
+// Test of the bits `bits` of a wave-uniform mask, as a scalar branch
+// condition of its own: the empty asm statement stops the compiler from
+// sharing one test between several branches, which it would otherwise keep as
+// a 64-bit lane mask in scalar registers (and spill them).
+__device__ __forceinline__ bool any_bits(uint32_t mask, uint32_t bits)
+{
+    asm volatile("" : "+s"(mask));
+    return (mask & bits) != 0u;
+}
+
 // Error-free transformations (Knuth's TwoSum; the FMA form of the exact
 // product): s + t = a + b and p + e = a b exactly in binary32.  Contraction is
 // off so that the compiler cannot fuse a product into a later sum.
@@ -244,7 +254,7 @@ __device__ __forceinline__ void flow_row(const float* K, uint32_t mask, v3<float
     bool first = true;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        if (mask & (1u << (3 * R + c))) {
+        if (any_bits(mask, 1u << (3 * R + c))) {
             float p, e;
             two_prod(K[3 * R + c], hc[c], p, e);
             small = small + __builtin_fmaf(K[3 * R + c], lc[c], e);
@@ -261,17 +271,25 @@ __device__ __forceinline__ void flow_row(const float* K, uint32_t mask, v3<float
     }
 }
 
-// K v for the entries of K marked in `mask` (wave-uniform; the others are
-// known to be zero in every lane), as fused multiply-adds in row order.
-__device__ __forceinline__ v3<float> masked_mat3(const float* K, uint32_t mask, v3<float> v)
+// K (h + l) of a compensated position (h, l) for the entries of K marked in
+// `mask` (wave-uniform; the others are known to be zero in every lane), as
+// fused multiply-adds in row order, h before l for each entry.  The empty asm
+// statement keeps each test a scalar branch: without it the compiler computes
+// all nine products and picks the results with vector selects, which costs
+// more than the products a typical kappa needs.
+__device__ __forceinline__ v3<float> masked_mat3(const float* K, uint32_t mask, v3<float> h, v3<float> l)
 {
-    const float vc[3] = {v.x, v.y, v.z};
+    const float hc[3] = {h.x, h.y, h.z};
+    const float lc[3] = {l.x, l.y, l.z};
     float r[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            if (mask & (1u << (3 * a + c))) r[a] = __builtin_fmaf(K[3 * a + c], vc[c], r[a]);
+            if (any_bits(mask, 1u << (3 * a + c))) {
+                r[a] = __builtin_fmaf(K[3 * a + c], lc[c], __builtin_fmaf(K[3 * a + c], hc[c], r[a]));
+                asm volatile("" : "+v"(r[a]));
+            }
     return {r[0], r[1], r[2]};
 }
 

@@ -193,7 +193,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     const T hop_h2 = T(2.0 * a.ph.dt / a.ph.zeta_s);                    // 2 dt / zeta_s
     const T hop_e2q = glauber_exp_scale<T>(3.0 / (4.0 * a.ph.ns));     // Glauber argument scale 3/(4 N_s)
     const T asd = T(sqrt(a.ph.ns / 3.0));                               // anchor offset s.d.
-    const uint32_t k0 = a.ph.key0, k1 = a.ph.key1;
+    uint32_t k0 = a.ph.key0, k1 = a.ph.key1;
 
     T kdt[9];  // dt kappa of the chain's element
     uint32_t kmask = 0;  // entries of kappa that are nonzero in some chain of the wavefront
@@ -390,7 +390,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         // the flow terms test the bits of kmask every step; recomputing those
         // tests (scalar ops) is cheaper than keeping nine hoisted conditions
         // in scalar registers across the loop, which spilled
-        if constexpr (FL) asm volatile("" : "+s"(kmask));
+        // Likewise the random streams' round keys (key + r x Weyl constant)
+        // are recomputed by scalar adds at every draw rather than kept in
+        // twenty scalar registers, which the flow variants would spill.
+        if constexpr (FL) asm volatile("" : "+s"(kmask), "+s"(k0), "+s"(k1));
         const int64_t g = g0 + step;
         if constexpr (RP) {
 #pragma unroll
@@ -533,24 +536,33 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
                         }
                     }
                 }
+                // The tests of kmask (wave-uniform) stay outside the
+                // per-lane conditions: nested inside them they would be
+                // turned into lane masks and vector selects.
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
+                    const v3<T> f = masked_mat3(kdt, kmask, rh[b], rl[b]);
                     if (li * B + b < n && !chain_stretch) {
                         v3<T> inc = plain_inc(b);
-                        if (chain_flow) inc = inc + (masked_mat3(kdt, kmask, rh[b]) + masked_mat3(kdt, kmask, rl[b]));
+                        if (chain_flow) inc = inc + f;
                         cadd3(rh[b], rl[b], inc);
                     }
                 }
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    if (s[b] >= 0 && chain_flow) {
-                        v3<T> big, small;
+                    const bool adv = s[b] >= 0 && chain_flow;
+                    v3<T> big, small;
+                    if (any_bits(kmask, 0x007u)) {
                         flow_row<0>(kdt, kmask, ah[b], al[b], big.x, small.x);
+                        if (adv) cadd_big(ah[b].x, al[b].x, big.x, small.x);
+                    }
+                    if (any_bits(kmask, 0x038u)) {
                         flow_row<1>(kdt, kmask, ah[b], al[b], big.y, small.y);
+                        if (adv) cadd_big(ah[b].y, al[b].y, big.y, small.y);
+                    }
+                    if (any_bits(kmask, 0x1C0u)) {
                         flow_row<2>(kdt, kmask, ah[b], al[b], big.z, small.z);
-                        if (kmask & 0x007u) cadd_big(ah[b].x, al[b].x, big.x, small.x);
-                        if (kmask & 0x038u) cadd_big(ah[b].y, al[b].y, big.y, small.y);
-                        if (kmask & 0x1C0u) cadd_big(ah[b].z, al[b].z, big.z, small.z);
+                        if (adv) cadd_big(ah[b].z, al[b].z, big.z, small.z);
                     }
                 }
             } else {
