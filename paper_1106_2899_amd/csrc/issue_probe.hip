@@ -28,7 +28,7 @@ enum Op : int {
   RCP_F32, FMA_F64, ADD_F64, MUL_F64, CVT_F64_F32, CVT_F32_F64, SUB_F32, MAX_F32, MED3_F32, SUB_F32_DPP,
   MOV_B32, MOV_B64, AND_B32, OR_B32, SUB_U32, MAX_I32, ALIGNBIT_B32, LSHL_ADD_U32, ADD3_U32, PERM_B32, BFE_U32,
   LSHR_B32, BCNT_U32, MBCNT_LO, MUL_U32_U24, CNDMASK_VCC, CMP_NE_U32_VCC, CMP_LT_I32_SGPR, CMP_LT_F32_VCC,
-  ADD_CO_U32, READFIRSTLANE, N_OPS
+  ADD_CO_U32, READFIRSTLANE, CMP_CNDMASK_VCC, CMP_CNDMASK_SGPR, N_OPS
 };
 
 const char* const kNames[N_OPS] = {
@@ -39,7 +39,8 @@ const char* const kNames[N_OPS] = {
     "v_med3_f32", "v_sub_f32_dpp", "v_mov_b32", "v_mov_b64", "v_and_b32", "v_or_b32", "v_sub_u32", "v_max_i32",
     "v_alignbit_b32", "v_lshl_add_u32", "v_add3_u32", "v_perm_b32", "v_bfe_u32", "v_lshrrev_b32",
     "v_bcnt_u32_b32", "v_mbcnt_lo_u32_b32", "v_mul_u32_u24", "v_cndmask_b32 (vcc)", "v_cmp_ne_u32 (vcc)",
-    "v_cmp_lt_i32_e64 (sgpr pair)", "v_cmp_lt_f32 (vcc)", "v_add_co_u32", "v_readfirstlane_b32"};
+    "v_cmp_lt_i32_e64 (sgpr pair)", "v_cmp_lt_f32 (vcc)", "v_add_co_u32", "v_readfirstlane_b32",
+    "v_cmp_lt_f32 + v_cndmask_b32 through vcc (pair)", "v_cmp_lt_f32_e64 + v_cndmask_b32_e64 through an sgpr pair (pair)"};
 
 #define R8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
@@ -263,6 +264,23 @@ __global__ __launch_bounds__(256) void k_probe(int iters, float* sink) {
       } else if constexpr (OP == ADD_CO_U32) {
 #define X(i) asm volatile("v_add_co_u32 %0, vcc, %0, %1" : "+v"(u[i]) : "v"(ub) : "vcc");
         R8(X)
+#undef X
+      } else if constexpr (OP == CMP_CNDMASK_VCC) {
+        // 16 compare + select pairs per iteration (32 instructions)
+#define X(i)                                                                                         \
+  if ((i & 1) == 0)                                                                                  \
+    asm volatile("v_cmp_lt_f32 vcc, %1, %2\n\tv_cndmask_b32 %0, %0, %3, vcc" : "+v"(u[i]) : "v"(f[i]), \
+                 "v"(fb), "v"(ub) : "vcc");
+        R8(X) R8(X)
+#undef X
+      } else if constexpr (OP == CMP_CNDMASK_SGPR) {
+#define X(i)                                                                                     \
+  if ((i & 1) == 0) {                                                                            \
+    uint64_t c;                                                                                  \
+    asm volatile("v_cmp_lt_f32_e64 %1, %2, %3\n\tv_cndmask_b32_e64 %0, %0, %4, %1"              \
+                 : "+v"(u[i]), "=&s"(c) : "v"(f[i]), "v"(fb), "v"(ub));                            \
+  }
+        R8(X) R8(X)
 #undef X
       } else if constexpr (OP == READFIRSTLANE) {
 #define X(i) asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(sg[i]) : "v"(u[i]));
