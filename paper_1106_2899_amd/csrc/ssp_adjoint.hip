@@ -275,13 +275,26 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     auto step_back = [&](const int m, auto QC) {
         constexpr int qs = decltype(QC)::value;
         const int64_t mg = a.m0 + m;
+        // The ring's last slot is refilled at the start of the step, into
+        // fresh registers: at the loop's wrap-around the compiler moves that
+        // slot's registers, which waits for its load, and the load has then
+        // had a whole step to arrive.  The other slots are refilled at the
+        // end of their step, in place.
+        int s_cur[B];
+        v3<T> R_cur[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            s_cur[b] = s_pre[qs][b];
+            R_cur[b] = R_pre[qs][b];
+        }
+        if constexpr (qs == kAhead - 1) prefetch(qs, m - kAhead);
         int sm[B], s1[B];
         v3<T> Rm[B], Am[B];
         bool any_cr = false;
         bool cr[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            sm[b] = li * B + b < n ? checked(s_pre[qs][b]) : -1;
+            sm[b] = li * B + b < n ? checked(s_cur[b]) : -1;
             s1[b] = s_next[b];
             s_next[b] = sm[b];
             if (SW || m == 0)
@@ -325,7 +338,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            Rm[b] = R_pre[qs][b];
+            Rm[b] = R_cur[b];
             cr[b] = sm[b] < 0 && s1[b] >= 0;
             any_cr |= cr[b];
             Am[b] = zero3<T>();
@@ -456,7 +469,7 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
         }
         // row m - kAhead into this step's ring slot, issued after the last
         // use of row m, so that the load can reuse its registers
-        prefetch(qs, m - kAhead);
+        if constexpr (qs != kAhead - 1) prefetch(qs, m - kAhead);
         wave_sync();
     };
     static_assert(kAhead == 3, "the loop below is unrolled over a ring of three rows");
