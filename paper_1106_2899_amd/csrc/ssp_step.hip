@@ -91,18 +91,65 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v)
+// Wavefront-ordered LDS accesses of the slot masks.
+template <typename M> __device__ __forceinline__ void lmask_store(M* p, M v)
 {
     __hip_atomic_store(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
-__device__ __forceinline__ uint32_t lds_load(uint32_t* p)
+template <typename M> __device__ __forceinline__ M lmask_load(M* p)
 {
     return __hip_atomic_load(p, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
-__device__ __forceinline__ void lds_min(uint32_t* p, uint32_t v)
+template <typename M> __device__ __forceinline__ void lmask_or(M* p, M v)
 {
-    __hip_atomic_fetch_min(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_fetch_or(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
+
+// Index of the lowest set bit, or -1 (all bits set) when there is none, as
+// the hardware's find-first-bit gives it.
+__device__ __forceinline__ uint32_t first_bit(uint32_t x)
+{
+    uint32_t r;
+    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// The slots of a segment anchored at one bead: bit j of the mask for slot j,
+// in 32-bit words.
+template <int kCap> struct SlotMask {
+    static constexpr int kWords = (kCap + 31) / 32;
+    uint32_t w[kWords];
+
+    __device__ __forceinline__ bool any() const
+    {
+        uint32_t o = 0;
+#pragma unroll
+        for (int q = 0; q < kWords; ++q) o |= w[q];
+        return o != 0;
+    }
+    // lowest slot in the mask, -1 when it is empty
+    __device__ __forceinline__ int lowest() const
+    {
+        uint32_t r = first_bit(w[0]);
+#pragma unroll
+        for (int q = 1; q < kWords; ++q) r = min(r, first_bit(w[q]) | (32u * q));  // -1 stays -1
+        return (int)r;
+    }
+    // removes the lowest slot
+    __device__ __forceinline__ void drop()
+    {
+        bool below = true;  // no slot in the words below
+#pragma unroll
+        for (int q = 0; q < kWords; ++q) {
+            const uint32_t v = w[q];
+            if (q == 0)
+                w[q] = v & (v - 1);  // no change when zero
+            else
+                w[q] = below ? (v & (v - 1)) : v;
+            below = below && v == 0;
+        }
+    }
+};
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
@@ -122,16 +169,16 @@ template <typename T> __device__ __forceinline__ bool finite3(v3<T> v)
 
 // Wave-private LDS: the bead records double as the transpose buffer of the
 // stress sums ([64 lanes][12] FP64), which is used only after the records of
-// a step have been consumed.
+// a step have been consumed, and as the beads' slot masks of the force
+// gather, which is done before the step's records are written.
 // SAMP: room for the stress-sample partials (a replay samples nothing, and
 // without them its LDS no longer limits the waves per SIMD).
-template <typename T, int B, bool SAMP> struct WaveLds {
+template <typename T, int W, int B, bool SAMP> struct WaveLds {
     static constexpr int kRecBytes = (int)sizeof(BeadRec<T>) * kWaveSize * B;
     static constexpr int kSumBytes = SAMP ? (int)sizeof(double) * kWaveSize * kSampleValues : 0;
     static constexpr int kShared = kRecBytes > kSumBytes ? kRecBytes : kSumBytes;
     alignas(16) unsigned char shared[kShared];
-    Off4<T> off[kWaveSize * B];
-    uint32_t first[kWaveSize * B];
+    Off4<T> off[(kWaveSize / W) * (W * B + 1)];  // per segment: a zero entry, then the slots
 };
 
 // The step, for the kernels below.  K1: construction by the K = 1 rule (one
@@ -155,7 +202,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     constexpr int kChainsPerWave = kWaveSize / W;
     constexpr int kCap = W * B;  // bead capacity of a segment
 
-    __shared__ WaveLds<T, B, !RP> lds[kWavesPerGroup];
+    __shared__ WaveLds<T, W, B, !RP> lds[kWavesPerGroup];
     // creation thresholds for p_K and 2 p_K, K = 0..kMaxBeads, read every step
     __shared__ uint32_t thr[2 * (kMaxBeads + 1)];
     for (int q = threadIdx.x; q < 2 * (kMaxBeads + 1); q += kGroupThreads) thr[q] = a.thr[q];
@@ -179,11 +226,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     const int64_t off = valid ? a.ct.off[chain] : 0;
     const uint32_t gid = valid ? a.ct.gid[chain] : 0u;
     const int elem = valid ? a.ct.elem[chain] : 0;
-    uint32_t* lfirst = lds[wv].first;
     BeadRec<T>* rec = reinterpret_cast<BeadRec<T>*>(lds[wv].shared);
     double* sums = reinterpret_cast<double*>(lds[wv].shared);
-    Off4<T>* offs = lds[wv].off;
     const int lbase = seg * kCap;  // this segment's first entry in the LDS arrays
+    // this segment's slot offsets: slot j at offs[j], a zero entry at offs[-1]
+    Off4<T>* offs = lds[wv].off + seg * (kCap + 1) + 1;
+    if (li == 0) offs[-1] = Off4<T>{};
+    constexpr int kMaskWords = SlotMask<kCap>::kWords;
+    static_assert(4 * kMaskWords <= (int)sizeof(BeadRec<T>), "the slot masks fit in the records");
+    uint32_t* lmask = reinterpret_cast<uint32_t*>(lds[wv].shared);
+    auto mask_at = [&](int bead) { return (lbase + bead) * kMaskWords; };
+    uint32_t mbit[B];  // this lane's slots: their bit and word in a mask
+    int mbit_word[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        mbit[b] = 1u << ((li * B + b) % 32);
+        mbit_word[b] = (li * B + b) / 32;
+    }
 
     // Step constants with dt folded in: the move is
     //   R += sqrt(2 dt) w + 3 dt (b_right - b_left) - (3/N_s) dt sum_j d_j + dt kappa R.
@@ -277,7 +336,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
             o.v[1] = d[b].y;
             o.v[2] = d[b].z;
             o.v[3] = T(0);
-            offs[lbase + li * B + b] = o;
+            offs[li * B + b] = o;
         }
         wave_sync();
     };
@@ -404,33 +463,25 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
 
         // ---- substep 1a: slip-spring force, sum of d_j over the springs of each
-        // bead, delivered in increasing slot order (one spring per bead per
-        // round).  The first round's LDS operations are issued before the
-        // step's noise is computed (it does not depend on them), so that their
-        // latency runs under that arithmetic.
-        v3<T> acc[B];
-        bool pend[B];
-        bool any_pend = false;
+        // bead in increasing slot order.  Every occupied slot sets its bit in
+        // its bead's slot mask (LDS atomics of one wavefront complete in
+        // order, so the clearing stores land first); each bead then reads its
+        // mask and adds the staged offsets of its set bits lowest first.  The
+        // mask round trip is issued before the step's noise is computed (it
+        // does not depend on it), so that its latency runs under that
+        // arithmetic; the first two offsets of every bead are read together.
+        SlotMask<kCap> mw[B];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            acc[b] = zero3<T>();
-            pend[b] = s[b] >= 0;
-            any_pend |= pend[b];
-        }
-        const bool gather = wave_any(any_pend);
-        uint32_t got[B], chk[B];
-        if (gather) {
+        for (int b = 0; b < B; ++b)
 #pragma unroll
-            for (int b = 0; b < B; ++b) lds_store(&lfirst[lbase + li * B + b], 0xFFFFFFFFu);
+            for (int w = 0; w < kMaskWords; ++w) lmask_store(&lmask[mask_at(li * B + b) + w], 0u);
 #pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (pend[b]) lds_min(&lfirst[lbase + s[b]], (uint32_t)(lbase + li * B + b));
+        for (int b = 0; b < B; ++b)
+            if (s[b] >= 0) lmask_or(&lmask[mask_at(s[b]) + mbit_word[b]], mbit[b]);
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                got[b] = lds_load(&lfirst[lbase + li * B + b]);
-                chk[b] = lds_load(&lfirst[lbase + (s[b] > 0 ? s[b] : 0)]);
-            }
-        }
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int w = 0; w < kMaskWords; ++w) mw[b].w[w] = lmask_load(&lmask[mask_at(li * B + b) + w]);
 
         // ---- substep 1b, first part: sqrt(2 dt) w of this step.
         v3<T> noise[B];
@@ -447,39 +498,34 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
             }
         }
 
-        // ---- substep 1a, completion of the first round and further rounds.
-        // Every round delivers at least one spring per bead that still has
-        // one, so kCap rounds always suffice; the cap only guards against a hang.
-        if (gather) {
-            any_pend = false;
+        // ---- substep 1a, completion: the first two springs of every bead
+        // (read unconditionally: a missing one reads the zero entry), then
+        // the rare beads with more.  The sum is never -0, so adding +0 for a
+        // missing spring changes nothing.
+        v3<T> acc[B];
+        bool more = false;
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (pend[b] && chk[b] == (uint32_t)(lbase + li * B + b)) pend[b] = false;
-                any_pend |= pend[b];
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (got[b] != 0xFFFFFFFFu) acc[b] = acc[b] + unpack3(offs[got[b]]);
+        for (int b = 0; b < B; ++b) {
+            const v3<T> o0 = unpack3(offs[mw[b].lowest()]);
+            mw[b].drop();
+            const v3<T> o1 = unpack3(offs[mw[b].lowest()]);
+            mw[b].drop();
+            acc[b] = (zero3<T>() + o0) + o1;
+            more |= mw[b].any();
         }
-        for (int round = 1; round <= kCap && wave_any(any_pend); ++round) {
+        if (wave_any(more)) {
+            do {
+                more = false;
 #pragma unroll
-            for (int b = 0; b < B; ++b) lds_store(&lfirst[lbase + li * B + b], 0xFFFFFFFFu);
-#pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (pend[b]) lds_min(&lfirst[lbase + s[b]], (uint32_t)(lbase + li * B + b));
-#pragma unroll
-            for (int b = 0; b < B; ++b) got[b] = lds_load(&lfirst[lbase + li * B + b]);
-            any_pend = false;
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (pend[b] && lds_load(&lfirst[lbase + s[b]]) == (uint32_t)(lbase + li * B + b)) pend[b] = false;
-                any_pend |= pend[b];
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (got[b] != 0xFFFFFFFFu) acc[b] = acc[b] + unpack3(offs[got[b]]);
+                for (int b = 0; b < B; ++b) {
+                    if (mw[b].any()) {
+                        acc[b] = acc[b] + unpack3(offs[mw[b].lowest()]);
+                        mw[b].drop();
+                    }
+                    more |= mw[b].any();
+                }
+            } while (wave_any(more));
         }
-        if (any_pend) atomicOr(a.flags, kFlagInternal);
 
         // ---- substep 1b: Euler-Maruyama for beads, advection for anchors.
         // FP32 under flow: positions drift and stretch far from the origin
