@@ -462,6 +462,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         const bool even = (g & 1) == 0;  // wave-uniform
         const int64_t kp = g >> 1;       // step pair: counter step word of the random streams
 
+        // The counts that substep 3 takes from the post-hop state: a hop moves
+        // a spring but never fills or frees a slot, so they are those of the
+        // state before the step, and the thresholds' LDS reads are issued here.
+        int z = 0;
+        int first_empty = kCap;  // lowest empty slot of the chain (K = 1 rule)
+#pragma unroll
+        for (int b = 0; b < B && !RP; ++b) {
+            z += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
+            if constexpr (K1) {
+                const uint64_t m = __ballot(s[b] < 0 && li * B + b < n) & seg_mask<W>(sb);
+                if (m) first_empty = min(first_empty, ((int)__builtin_ctzll(m) - sb) * B + b);
+            }
+        }
+        const int K = K1 ? (z < n ? 1 : 0) : n - z;
+        const uint32_t t1 = thr[K < 0 ? 0 : K];
+        const uint32_t t2 = thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
+
         // ---- substep 1a: slip-spring force, sum of d_j over the springs of each
         // bead in increasing slot order.  Every occupied slot sets its bit in
         // its bead's slot mask (LDS atomics of one wavefront complete in
@@ -703,20 +720,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
 
         // ---- substep 3: destruction at the ends and construction, all from the
         // post-hop state.  K = C - Z attempts (every empty slot once), or with
-        // the K = 1 rule a single attempt by the segment's lowest empty slot.
-        int z = 0;
-        int first_empty = kCap;  // lowest empty slot of the chain (K = 1 rule)
-#pragma unroll
-        for (int b = 0; b < B && !RP; ++b) {
-            z += __popcll(__ballot(s[b] >= 0) & seg_mask<W>(sb));
-            if constexpr (K1) {
-                const uint64_t m = __ballot(s[b] < 0 && li * B + b < n) & seg_mask<W>(sb);
-                if (m) first_empty = min(first_empty, ((int)__builtin_ctzll(m) - sb) * B + b);
-            }
-        }
-        const int K = K1 ? (z < n ? 1 : 0) : n - z;
-        const uint32_t t1 = thr[K < 0 ? 0 : K];
-        const uint32_t t2 = thr[kMaxBeads + 1 + (K < 0 ? 0 : K)];
+        // the K = 1 rule a single attempt by the segment's lowest empty slot
+        // (both counted at the start of the step).
         int create_at[B];
         bool destroyed[B];
         bool any_create = false;
