@@ -12,10 +12,10 @@
 //   - per-bead records {R hi, R lo, bond right, bond left} are staged in a
 //     wave-private LDS array after the move; slots read the record of their
 //     bead for the hop, for new anchors and for the anchor offsets;
-//   - the slot -> bead force scatter is a deterministic gather: in rounds,
-//     pending springs ds_min their slot index into their bead's LDS word and
-//     each bead adds the winner's offset d (read from LDS) in increasing slot
-//     order; no float atomics, so runs are bitwise reproducible;
+//   - the slot -> bead force scatter is a deterministic gather: every spring
+//     sets its slot's bit in its bead's LDS mask and each bead adds the
+//     offsets d of its set bits (read from LDS) in increasing slot order; no
+//     float atomics, so runs are bitwise reproducible;
 //   - stress sums: every lane writes its FP64 partial sums to LDS and the
 //     lanes of the segment add one column each in lane order (deterministic).
 //
