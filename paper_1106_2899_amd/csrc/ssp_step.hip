@@ -235,7 +235,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     constexpr int kMaskWords = SlotMask<kCap>::kWords;
     static_assert(4 * kMaskWords <= (int)sizeof(BeadRec<T>), "the slot masks fit in the records");
     uint32_t* lmask = reinterpret_cast<uint32_t*>(lds[wv].shared);
-    auto mask_at = [&](int bead) { return (lbase + bead) * kMaskWords; };
+    // word w of a bead's mask: the wavefront's words w side by side, so that
+    // the lanes' accesses to their own beads fall in distinct banks
+    auto mask_at = [&](int bead, int w) { return w * (kWaveSize * B) + lbase + bead; };
     uint32_t mbit[B];  // this lane's slots: their bit and word in a mask
     int mbit_word[B];
 #pragma unroll
@@ -491,14 +493,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
-            for (int w = 0; w < kMaskWords; ++w) lmask_store(&lmask[mask_at(li * B + b) + w], 0u);
+            for (int w = 0; w < kMaskWords; ++w) lmask_store(&lmask[mask_at(li * B + b, w)], 0u);
 #pragma unroll
         for (int b = 0; b < B; ++b)
-            if (s[b] >= 0) lmask_or(&lmask[mask_at(s[b]) + mbit_word[b]], mbit[b]);
+            if (s[b] >= 0) lmask_or(&lmask[mask_at(s[b], mbit_word[b])], mbit[b]);
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
-            for (int w = 0; w < kMaskWords; ++w) mw[b].w[w] = lmask_load(&lmask[mask_at(li * B + b) + w]);
+            for (int w = 0; w < kMaskWords; ++w) mw[b].w[w] = lmask_load(&lmask[mask_at(li * B + b, w)]);
 
         // ---- substep 1b, first part: sqrt(2 dt) w of this step.
         v3<T> noise[B];
