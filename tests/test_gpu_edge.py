@@ -1,8 +1,9 @@
 """Edge cases of the step on the GPU against the oracle: the smallest chain
 (N = 2, both beads are ends), workgroups with a ragged tail (fewer chains than
-a group holds, a wave only partly filled), zero-step calls, and one-step
+a group holds, a wave only partly filled), zero-step calls, one-step
 launches that start at odd steps (the step-pair random streams rebuild their
-carry)."""
+carry), and states with many springs on one bead (the force gather adds them
+in slot order, over every width of the beads' slot masks)."""
 import numpy as np
 import pytest
 
@@ -33,9 +34,17 @@ def _bonds_offsets(R, A, S, lengths):
     return np.concatenate(b), np.concatenate(d)
 
 
-def _compare_run(lengths, precision, steps, seed, kappa=None, launch=1):
+def _compare_run(lengths, precision, steps, seed, kappa=None, launch=1, state=None, mapping=None):
     e = _ens(np.array(lengths), precision=precision, seed=seed, corr_levels=0).init()
     o = oracle.Ensemble(lengths, seed=seed).init()
+    if mapping is not None:
+        e.set_mapping(*mapping)
+    if state is not None:
+        R, A, S = state
+        e.write_state(R, A, S)
+        o.R[:] = R
+        o.A[:] = A
+        o.S[:] = S
     kap = None if kappa is None else np.asarray(kappa)
     worst = 0.0
     for t in range(0, steps, launch):
@@ -51,6 +60,41 @@ def _compare_run(lengths, precision, steps, seed, kappa=None, launch=1):
         worst = max(worst, err)
         assert err <= TOL[precision], (t, err)
     return worst
+
+
+def _crowded_state(lengths, rng):
+    """Random-walk chains whose slots pile onto few beads: chains 0, 3, ...
+    hold every slot on bead 5 (or the last bead of a shorter chain), chains
+    1, 4, ... alternate their slots between the two ends, and the others put
+    about half of their slots on bead 1 and the rest anywhere or empty."""
+    R, A, S = [], [], []
+    for c, n in enumerate(lengths):
+        r = np.cumsum(rng.normal(0.0, np.sqrt(1.0 / 3.0), (n, 3)), axis=0)
+        if c % 3 == 0:
+            s = np.full(n, min(5, n - 1))
+        elif c % 3 == 1:
+            s = np.where(np.arange(n) % 2 == 0, 0, n - 1)
+        else:
+            s = np.where(rng.random(n) < 0.5, 1, rng.integers(-1, n, n))
+        a = r[np.maximum(s, 0)] + rng.normal(0.0, np.sqrt(0.5 / 3.0), (n, 3))
+        a[s < 0] = 0.0
+        R.append(r)
+        A.append(a)
+        S.append(s)
+    return np.concatenate(R), np.concatenate(A), np.concatenate(S).astype(np.int32)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,W,B", [(8, 8, 1), (32, 32, 1), (32, 16, 2), (32, 64, 1), (64, 64, 1), (64, 32, 2),
+                                   (128, 64, 2)])
+def test_crowded_beads_gather_in_slot_order(precision, N, W, B):
+    """Up to N springs on one bead, in every mask width (one, two and four
+    32-bit words per bead) and with two beads per lane; launches of four
+    steps, so the masks are rebuilt inside a launch."""
+    lengths = [N] * 6
+    state = _crowded_state(lengths, np.random.default_rng(1000 + N + W + B))
+    worst = _compare_run(lengths, precision, 8, seed=26, launch=4, state=state, mapping=(N, N, W, B))
+    print(precision, N, W, B, "crowded worst", worst)
 
 
 def test_single_two_bead_chain_fp64():
