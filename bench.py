@@ -15,12 +15,13 @@ VALU roofline of the step kernel (launch durations from HIP events on the
 launch stream); the adjoint/forward time ratio (a checkpoint every 100 steps,
 and the window stored as one segment); the start-up shear (4096 elements x 256
 chains, 2e4 steps) and polydisperse (2^18 chains, 1e4 steps) workloads at full
-length, each with its own roofline fraction; and, from the CPU leg, the FP64
-oracle timed on the host cores (all threads and one thread, with the CPU
-model) and the accuracy of every number against that oracle: the per-step
-error and ties of sampled chains in lock step, G(t) of the headline run in
-units of its standard error, the final state of the FP64 run, and the
-adjoint's per-chain gradients.
+length, each with its own roofline fraction; the shapes of the paper's
+timing table (context, beside the paper's GPU seconds); and, from the CPU
+leg, the FP64 oracle timed on the host cores (all threads and one thread,
+with the CPU model) and the accuracy of every number against that oracle:
+the per-step error and ties of sampled chains in lock step, G(t) of the
+headline run in units of its standard error, the final state of the FP64
+run, and the adjoint's per-chain gradients.
 """
 from __future__ import annotations
 
@@ -38,6 +39,13 @@ CHAINS, BEADS, SAMPLE_EVERY = 16384, 32, 10
 MD_STEPS_PER_BENCH_STEP = 5000  # 20 bench steps = the whole 1e5-step run
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: full-rate VALU lane-issue slots/s
 QUEUE_KERNEL = "k_step_queue<float,32,1,false,false>"
+# The shapes of the paper's timing table (Sec. 4): N x M with N M = 65536
+# beads, 1e4 steps from equilibrium, at rest and under simple shear at rate
+# 0.05, with the seconds the paper's GPU (FP32, 2009) took for each.
+PAPER_TABLE_SHAPES = [(16, 4096, 0.0, 0.897), (16, 4096, 0.05, 0.895), (32, 2048, 0.0, 0.902),
+                      (32, 2048, 0.05, 0.895), (64, 1024, 0.0, 0.870), (64, 1024, 0.05, 0.863),
+                      (128, 512, 0.0, 0.845), (128, 512, 0.05, 0.840)]
+PAPER_TABLE_STEPS = 10_000
 
 
 def _log(msg):
@@ -354,6 +362,45 @@ def flow_workload(w, tune):
     return out
 
 
+def _shear(rate):
+    import numpy as np
+
+    k = np.zeros((3, 3))
+    k[0, 1] = rate
+    return k
+
+
+def paper_table_shapes():
+    """Context rows: the shapes of the paper's timing table on this GPU (FP32,
+    stress sampled every 10 steps, no correlator), each run as one graph
+    launch of all 1e4 steps after a warm-up run of the same length, beside
+    the paper's GPU seconds.  65536 beads fill a few percent of the
+    wavefront slots, so these runs are latency-bound and carry no roofline."""
+    import torch
+
+    from paper_1106_2899_amd.ensemble import Ensemble
+
+    rows = []
+    for N, M, rate, paper_s in PAPER_TABLE_SHAPES:
+        e = Ensemble(N, M, precision="fp32", seed=7, sample_every=SAMPLE_EVERY, corr_levels=0, use_graph=True)
+        kap = None if rate == 0.0 else torch.as_tensor(_shear(rate).reshape(1, 9), dtype=torch.float64, device="cuda")
+        e.init()
+        e.step(PAPER_TABLE_STEPS, kap)  # graph capture and a full warm-up run
+        torch.cuda.synchronize()
+        e.init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.step(PAPER_TABLE_STEPS, kap)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert torch.isfinite(e.stress()).all()
+        e.close()
+        rows.append({"shape": f"{N}x{M}", "shear_rate": rate, "steps": PAPER_TABLE_STEPS, "seconds": dt,
+                     "value": N * M * PAPER_TABLE_STEPS / dt, "unit": "bead-steps/s",
+                     "paper_gpu_seconds": paper_s, "speedup_over_paper_gpu": paper_s / dt})
+    return rows
+
+
 # ---------------------------------------------------------------- CPU leg --
 # The FP64 oracle (test infrastructure) on the host cores: its timing, and
 # the accuracy of every GPU number against it.
@@ -459,6 +506,24 @@ def cpu_leg(G_gpu, steps_gpu, eq_ensemble, flow_ws):
         ids = np.linspace(0, w.n_chains - 1, 8).astype(np.int64)
         out[name] = _lockstep_accuracy(ids, w.n_beads, kchain, w.seed, 1000)
         _log(f"lock step {name} done")
+    # the paper's timing-table shapes: the oracle in full at rest on all
+    # threads, and sampled chains of the sheared extremes in lock step
+    shapes = []
+    for N, M, rate, _ in PAPER_TABLE_SHAPES:
+        if rate != 0.0:
+            continue
+        o = oracle.Ensemble([N] * M, seed=7).init()
+        t0 = time.perf_counter()
+        o.run(PAPER_TABLE_STEPS, sample_every=SAMPLE_EVERY, keep_samples=False)
+        dt = time.perf_counter() - t0
+        shapes.append({"shape": f"{N}x{M}", "steps": PAPER_TABLE_STEPS, "seconds": dt, "threads": n_all,
+                       "value": N * M * PAPER_TABLE_STEPS / dt, "unit": "bead-steps/s"})
+    baseline["paper_table_shapes"] = shapes
+    _log("oracle on the paper's table shapes done")
+    for N, M in ((16, 4096), (128, 512)):
+        ids = np.linspace(0, M - 1, 8).astype(np.int64)
+        kchain = np.repeat(_shear(0.05).reshape(1, 9), M, axis=0)
+        out[f"paper_shape_{N}x{M}_shear_0.05"] = _lockstep_accuracy(ids, np.full(M, N), kchain, 7, 1000)
     # the FP64 equilibrium run: final state of every chain after 1e4 steps
     if eq_ensemble is not None:
         w1 = workloads.equilibrium_small()
@@ -598,6 +663,8 @@ def main():
     for name, w in flow_ws:
         out["flow_workloads"][name] = flow_workload(w, tune=name.startswith("poly"))
         _log(f"{name}: {out['flow_workloads'][name]['value']:.4g} bead-steps/s")
+    out["paper_table_shapes"] = paper_table_shapes()
+    _log("paper's table shapes done")
     if not args.no_cpu_baseline:
         baseline, acc = cpu_leg(G_gpu, steps_gpu, eq_ens, flow_ws)
         acc["adjoint_stored_window"] = adjoint_accuracy()

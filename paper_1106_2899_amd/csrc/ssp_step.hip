@@ -1007,6 +1007,9 @@ template <typename T, int W, int B, bool K1, bool FL> int resident_groups()
     return cached;
 }
 
+// Shortest time chunk of the persistent schedule, in steps.
+constexpr int kMinChunkSteps = 200;
+
 template <typename T, int W, int B, bool FL> hipError_t launch_f(const StepArgs& a, dim3 grid, hipStream_t s)
 {
     if (a.sched && !a.replay_s && !a.traj) {
@@ -1014,18 +1017,23 @@ template <typename T, int W, int B, bool FL> hipError_t launch_f(const StepArgs&
         auto kern = a.construct_rule == 1 ? k_step_queue<T, W, B, true, FL> : k_step_queue<T, W, B, false, FL>;
         const int r = a.construct_rule == 1 ? resident_groups<T, W, B, true, FL>() : resident_groups<T, W, B, false, FL>();
         StepArgs p = a;
-        // time chunks per wave task: the count (1..16, chunks of >= 64 steps)
-        // whose last round of units leaves the fewest wavefront slots idle,
-        // plus a small charge per chunk for re-reading and writing the state
+        // time chunks per wave task: the count (1..16, chunks of at least
+        // kMinChunkSteps) with the shortest estimated run, in units of the
+        // launch's length.  The slots take ceil(units / slots) rounds of units
+        // of 1/nc of the steps, but a wave task's chunks run one after
+        // another, so never fewer than nc rounds; each chunk is also charged a
+        // little for re-reading and writing the state.  With fewer wave tasks
+        // than slots this keeps one chunk: more would only park wavefronts
+        // that wait for their chains' previous chunk.
         const double slots = (double)std::max(1, r) * kWavesPerGroup;
         int best = 1;
-        double best_loss = 1e30;
+        double best_t = 1e30;
         for (int nc = 1; nc <= 16; ++nc) {
-            if (nc > 1 && (a.n_steps + nc - 1) / nc < 64) break;
-            const double rounds = (double)(a.n_wave_tasks * nc) / slots;
-            const double loss = (std::ceil(rounds) - rounds) / std::ceil(rounds) + 0.002 * nc;
-            if (loss < best_loss - 1e-12) {
-                best_loss = loss;
+            if (nc > 1 && (a.n_steps + nc - 1) / nc < kMinChunkSteps) break;
+            const double rounds = std::max(std::ceil((double)(a.n_wave_tasks * nc) / slots), (double)nc);
+            const double t = rounds / nc + 0.002 * nc;
+            if (t < best_t - 1e-12) {
+                best_t = t;
                 best = nc;
             }
         }

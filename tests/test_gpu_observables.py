@@ -67,11 +67,12 @@ def test_chunking_and_graph_invariance_bitwise():
 @pytest.mark.parametrize("steps", [1, 7, 300, 2000])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_persistent_schedule_equals_plain_launches_bitwise(precision, steps):
-    """ssp_step under the persistent schedule (time chunks of wavefronts'
-    chains taken from a queue) and under one wavefront per chain group give
-    the same state, correlator and element series bit for bit: mixed lengths
-    (several mapping groups), mixed flows, sampling every 3 steps, and launch
-    lengths from one step (one chunk) to several chunks."""
+    """ssp_step under the persistent schedule (units of wavefronts' chains
+    taken from a queue) and under one wavefront per chain group give the same
+    state, correlator and element series bit for bit: mixed lengths (several
+    mapping groups), mixed flows, sampling every 3 steps, launches from one
+    step to 2000.  With fewer wave tasks than wavefront slots every launch is
+    one time chunk; time chunks are covered by the test below."""
     N = [8, 16, 24, 32, 64, 100] * 40
     M = len(N)
     offs = np.array([0, M // 3, 2 * M // 3, M])
@@ -86,6 +87,31 @@ def test_persistent_schedule_equals_plain_launches_bitwise(precision, steps):
     for e in (a, b):
         e.step(steps, kap)
         e.step(steps)
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)
+    assert np.array_equal(a.correlator()["G"], b.correlator()["G"])
+    assert torch.equal(a.element_series(), b.element_series())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_persistent_schedule_time_chunks_equal_plain_launches_bitwise(precision):
+    """More wave tasks (7000) than wavefront slots, so that the persistent
+    schedule splits each 2000-step launch into time chunks whose units wait
+    for their chains' previous chunk: the same state, correlator and element
+    series as one wavefront per chain group, bit for bit."""
+    N = [32] * 14000
+    M = len(N)
+    offs = np.array([0, M // 2, M])
+    kap = np.zeros((2, 9))
+    kap[0, 1] = 0.3
+    kw = dict(precision=precision, seed=31, sample_every=10, corr_levels=8, corr_batches=4, series_capacity=500,
+              n_elements=2, element_offsets=offs, max_steps_per_launch=2000)
+    a = _ens(N, **kw).init()
+    b = _ens(N, **kw).init()
+    b.set_schedule(False)
+    for e in (a, b):
+        e.step(2000, kap)
+        e.step(2000)
     for x, y in zip(a.state(), b.state()):
         assert torch.equal(x, y)
     assert np.array_equal(a.correlator()["G"], b.correlator()["G"])
