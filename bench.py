@@ -372,18 +372,21 @@ def _shear(rate):
 
 def paper_table_shapes():
     """Context rows: the shapes of the paper's timing table on this GPU (FP32,
-    stress sampled every 10 steps, no correlator), each run as one graph
-    launch of all 1e4 steps after a warm-up run of the same length, beside
-    the paper's GPU seconds.  65536 beads fill a few percent of the
-    wavefront slots, so these runs are latency-bound and carry no roofline."""
+    stress sampled every 10 steps, no correlator), each with the mapping the
+    autotuner picks for it and run as one graph launch of all 1e4 steps after
+    a warm-up run of the same length, beside the paper's GPU seconds.  65536
+    beads fill a few percent of the wavefront slots, so these runs are
+    latency-bound and carry no roofline."""
     import torch
 
+    from paper_1106_2899_amd import autotune
     from paper_1106_2899_amd.ensemble import Ensemble
 
     rows = []
     for N, M, rate, paper_s in PAPER_TABLE_SHAPES:
         e = Ensemble(N, M, precision="fp32", seed=7, sample_every=SAMPLE_EVERY, corr_levels=0, use_graph=True)
         kap = None if rate == 0.0 else torch.as_tensor(_shear(rate).reshape(1, 9), dtype=torch.float64, device="cuda")
+        mapping = json.loads(autotune.tune(e, kap).to_json())["choices"]
         e.init()
         e.step(PAPER_TABLE_STEPS, kap)  # graph capture and a full warm-up run
         torch.cuda.synchronize()
@@ -395,7 +398,7 @@ def paper_table_shapes():
         dt = time.perf_counter() - t0
         assert torch.isfinite(e.stress()).all()
         e.close()
-        rows.append({"shape": f"{N}x{M}", "shear_rate": rate, "steps": PAPER_TABLE_STEPS, "seconds": dt,
+        rows.append({"shape": f"{N}x{M}", "shear_rate": rate, "mapping": mapping, "steps": PAPER_TABLE_STEPS, "seconds": dt,
                      "value": N * M * PAPER_TABLE_STEPS / dt, "unit": "bead-steps/s",
                      "paper_gpu_seconds": paper_s, "speedup_over_paper_gpu": paper_s / dt})
     return rows
