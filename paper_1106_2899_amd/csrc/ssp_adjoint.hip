@@ -95,11 +95,19 @@ __global__ void __launch_bounds__(kGroupThreads) k_adjoint(AdjointArgs a)
     const int sb = lane - li;
     const int64_t task = ((int64_t)blockIdx.x * kWavesPerGroup + wv) * kChainsPerWave + seg;
     const bool valid = task < a.n_tasks;
-    const int chain = valid ? a.tasks[task] : 0;
-    const int n = valid ? a.ct.n[chain] : 0;
-    const int64_t off = valid ? a.ct.off[chain] : 0;
-    const uint32_t gid = valid ? a.ct.gid[chain] : 0u;
-    const int elem = valid ? a.ct.elem[chain] : 0;
+    int chain = valid ? a.tasks[task] : 0;
+    int n = valid ? a.ct.n[chain] : 0;
+    int64_t off = valid ? a.ct.off[chain] : 0;
+    uint32_t gid = valid ? a.ct.gid[chain] : 0u;
+    int elem = valid ? a.ct.elem[chain] : 0;
+    if constexpr (W == kWaveSize) {
+        // one chain per wavefront: its table entries go to scalar registers
+        chain = wave_uniform(chain);
+        n = wave_uniform(n);
+        off = wave_uniform(off);
+        gid = wave_uniform(gid);
+        elem = wave_uniform(elem);
+    }
     const int lbase = seg * kCap;
     AdjRec<T>* rec = lds_rec[wv];
     uint32_t* cnt = lds_cnt[wv];

@@ -52,6 +52,13 @@ __device__ __forceinline__ double wave_uniform(double v)
     const int2 p = __builtin_bit_cast(int2, v);
     return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readfirstlane(p.x), __builtin_amdgcn_readfirstlane(p.y)));
 }
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int64_t wave_uniform(int64_t v)
+{
+    const int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(int64_t, make_int2(__builtin_amdgcn_readfirstlane(p.x), __builtin_amdgcn_readfirstlane(p.y)));
+}
 
 // u = ((w >> 9) + 1/2) 2^-23: 23 random bits, exactly representable in
 // binary32 and binary64, never 0 or 1.

@@ -221,11 +221,20 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     auto run = [&](const int64_t wtask, const int64_t g0, const int32_t n_steps, const int64_t q0) {
     const int64_t task = wtask * kChainsPerWave + seg;
     const bool valid = task < a.n_tasks;
-    const int chain = valid ? a.tasks[task] : 0;
-    const int n = valid ? a.ct.n[chain] : 0;
-    const int64_t off = valid ? a.ct.off[chain] : 0;
-    const uint32_t gid = valid ? a.ct.gid[chain] : 0u;
-    const int elem = valid ? a.ct.elem[chain] : 0;
+    int chain = valid ? a.tasks[task] : 0;
+    int n = valid ? a.ct.n[chain] : 0;
+    int64_t off = valid ? a.ct.off[chain] : 0;
+    uint32_t gid = valid ? a.ct.gid[chain] : 0u;
+    int elem = valid ? a.ct.elem[chain] : 0;
+    if constexpr (W == kWaveSize) {
+        // one chain per wavefront: its table entries go to scalar registers,
+        // and the addresses built from them stay scalar
+        chain = wave_uniform(chain);
+        n = wave_uniform(n);
+        off = wave_uniform(off);
+        gid = wave_uniform(gid);
+        elem = wave_uniform(elem);
+    }
     BeadRec<T>* rec = reinterpret_cast<BeadRec<T>*>(lds[wv].shared);
     double* sums = reinterpret_cast<double*>(lds[wv].shared);
     const int lbase = seg * kCap;  // this segment's first entry in the LDS arrays
@@ -357,14 +366,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     // the window is split into launches.
     constexpr bool kTraj = RP || ST;
     const int64_t trow0 = RP ? 0 : g0 - a.rec_g0;
+    // (the chain's row base and the lane's bead index are kept apart, so that
+    // with one chain per wavefront the 64-bit part of the address is scalar)
     auto store_r = [&](int row) {
-        const int64_t e = (trow0 + row) * a.total + off;
+        T* base = reinterpret_cast<T*>(a.traj) + 3 * ((trow0 + row) * a.total + off);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = li * B + b;
             if (i < n) {  // streamed out once, read back once by the adjoint: non-temporal
                 const v3<T> v = rh[b] + rl[b];
-                T* q = reinterpret_cast<T*>(a.traj) + 3 * (e + i);
+                T* q = base + 3u * (uint32_t)i;
                 __builtin_nontemporal_store(v.x, q);
                 __builtin_nontemporal_store(v.y, q + 1);
                 __builtin_nontemporal_store(v.z, q + 2);
@@ -372,7 +383,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
         }
     };
     auto store_a = [&](int row, int b) {
-        reinterpret_cast<v3<T>*>(a.traj2)[(trow0 + row) * a.total + off + li * B + b] = ah[b] + al[b];
+        v3<T>* base = reinterpret_cast<v3<T>*>(a.traj2) + ((trow0 + row) * a.total + off);
+        base[(uint32_t)(li * B + b)] = ah[b] + al[b];
     };
     if constexpr (kTraj) store_r(0);
     int64_t dcount = 0;  // storing forward: entries in this chain's destruction log
@@ -437,10 +449,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     // its latency runs under the previous step.
     int replay_next[B], replay_ahead[B];
     auto replay_load = [&](int64_t gs, int (&dst)[B]) {
+        const int8_t* row = a.replay_s + ((gs + 1 - a.rec_g0) * a.total + off);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = li * B + b;
-            dst[b] = (j < n) ? (int)a.replay_s[(gs + 1 - a.rec_g0) * a.total + off + j] : -1;
+            dst[b] = (j < n) ? (int)row[(uint32_t)j] : -1;
         }
     };
     if constexpr (RP) {
@@ -980,11 +993,12 @@ k_step_queue(StepArgs a)
 }
 
 // Replay of recorded slot rows (the adjoint's reverse pass re-creates each
-// segment's trajectory this way).  It samples no stress: without the sampling
-// code and its LDS partials, FP32 with one bead per lane fits 6 waves per SIMD
-// (79 VGPRs, 17 KB of LDS per group) with no spills.
+// segment's trajectory this way).  It samples no stress.  FP32 with one bead
+// per lane is held at 5 waves per SIMD (84 VGPRs, no spills): at 6 it spills
+// a few values, and every reload from scratch waits for all of the wave's
+// memory operations in flight, the trajectory stores included.
 template <typename T, int W, int B, bool FL>
-__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && B == 1 ? 6 : 1)))
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && B == 1 ? 5 : 1)))
 k_replay(StepArgs a)
 {
     step_body<T, W, B, false, true, false, FL, false>(a);
