@@ -179,6 +179,7 @@ template <typename T, int W, int B, bool SAMP> struct WaveLds {
     static constexpr int kShared = kRecBytes > kSumBytes ? kRecBytes : kSumBytes;
     alignas(16) unsigned char shared[kShared];
     Off4<T> off[(kWaveSize / W) * (W * B + 1)];  // per segment: a zero entry, then the slots
+    T kdt[(kWaveSize / W) * 9];                   // per segment: dt kappa (flow variants)
 };
 
 // The step, for the kernels below.  K1: construction by the K = 1 rule (one
@@ -265,17 +266,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     const T asd = T(sqrt(a.ph.ns / 3.0));                               // anchor offset s.d.
     uint32_t k0 = a.ph.key0, k1 = a.ph.key1;
 
-    T kdt[9];  // dt kappa of the chain's element
+    T kdt_v[9];  // dt kappa of the chain's element
     uint32_t kmask = 0;  // entries of kappa that are nonzero in some chain of the wavefront
     bool chain_flow = false;  // this lane's chain has a nonzero kappa
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        kdt[q] = T(0);
+        kdt_v[q] = T(0);
         if constexpr (FL) {
             const double kq = valid ? a.kappa[9 * elem + q] : 0.0;
-            kdt[q] = T(a.ph.dt * kq);
+            kdt_v[q] = T(a.ph.dt * kq);
             // one chain per wavefront: its element's kappa is wave-uniform
-            if constexpr (W == kWaveSize) kdt[q] = wave_uniform(kdt[q]);
+            if constexpr (W == kWaveSize) kdt_v[q] = wave_uniform(kdt_v[q]);
             if (wave_any(kq != 0.0)) kmask |= 1u << q;
             chain_flow |= kq != 0.0;
         }
@@ -283,7 +284,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a)
     const bool flow = FL && kmask != 0;
     // elongation (a positive diagonal entry of kappa) stretches chains without
     // bound above the Rouse instability: such chains take the error-free move
-    const bool chain_stretch = chain_flow && (kdt[0] > T(0) || kdt[4] > T(0) || kdt[8] > T(0));
+    const bool chain_stretch = chain_flow && (kdt_v[0] > T(0) || kdt_v[4] > T(0) || kdt_v[8] > T(0));
+    // With several chains per wavefront dt kappa differs between segments:
+    // it is kept in LDS (a row per segment) and read where the flow terms use
+    // it, instead of holding nine registers per lane across the steps.
+    constexpr bool kKdtLds = FL && W < kWaveSize;
+    T* const kdt_lds = lds[wv].kdt + seg * 9;
+    if constexpr (kKdtLds) {
+        if (li == 0) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) kdt_lds[q] = kdt_v[q];
+        }
+    }
+    const T* kdt;
+    if constexpr (kKdtLds)
+        kdt = kdt_lds;
+    else
+        kdt = kdt_v;
 
     v3<T> rh[B], rl[B], ah[B], al[B], d[B], br[B], bl[B];
     int s[B];
